@@ -490,7 +490,7 @@ def test_alpha_marginalisation_against_scipy_logsumexp():
     from scipy.special import logsumexp
     rng = np.random.default_rng(12)
     f = _tiny_facet(rng)
-    f.wsum *= 1e4
+    f.wsum *= 1e5
     knots = oracle.alpha_knots(0.3, 3.5, 7)
     logw = oracle.log_alpha_weights([1e-4], knots)[0]
     e1 = np.array([0.1, -0.4, 0.0])

@@ -1,0 +1,245 @@
+/*
+ * rlf.h -- C ABI of the MI355X (gfx950) RadioLensfit hot path.
+ *
+ * Implements the data-parallel core of Rivi & Miller, "RadioLensfit: an HPC
+ * tool for accurate galaxy shape measurement with SKA" (arXiv 2203.14071):
+ *   - the sky model, a sum over catalogue sources of the exponential-disk
+ *     visibility of Eq. 1 (Sec. 2.2);
+ *   - per-source extraction: subtract every other source, phase-shift to the
+ *     source, average into a coarse uv grid ("facet") whose field of view is
+ *     K times the scale length (Sec. 2.3);
+ *   - the shape fit: chi-squared likelihood of the facet under Eq. 1 at the
+ *     cell centres, flux marginalised analytically, scale length marginalised
+ *     numerically under a log-normal prior (Sec. 2.4), evaluated on a full
+ *     (e1, e2) grid, and the thresholded-moment estimate with the variance
+ *     test for bad fits (Sec. 2.4, 4.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented as "device" are HIP device pointers on the context's
+ *     device; "host" pointers are ordinary host memory.  The caller owns every
+ *     buffer it passes; the library owns only rlf_ctx and rlf_facets objects.
+ *   - Work is enqueued on the context's HIP stream and the call returns
+ *     without waiting, unless the entry point says it synchronises.  Results
+ *     are valid after rlf_sync() or any later synchronisation of that stream.
+ *   - Every call returns RLF_OK (0) or a negative rlf_status; nothing aborts.
+ *     rlf_last_error() returns a text description of the last failure on a
+ *     context.  A context is not thread-safe; use one per host thread.
+ *   - Complex arrays are interleaved (re, im).  Visibility arrays are indexed
+ *     [row * n_chan + chan] (channel fastest).
+ *   - Precision forms: RLF_FP64 computes everything in FP64 (complex128
+ *     visibilities, f64 weights).  RLF_MIXED forms and range-reduces phase
+ *     arguments in FP64 and runs sin/cos, the model and the likelihood in
+ *     FP32 with compensated (block-FP64) sums (complex64 visibilities, f32
+ *     weights).
+ */
+#ifndef RLF_H
+#define RLF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlf_ctx rlf_ctx;        /* opaque: device, stream, parameters, tables */
+typedef struct rlf_facets rlf_facets;  /* opaque: facet geometry + device buffers for one catalogue */
+
+typedef enum {
+  RLF_OK = 0,
+  RLF_EINVAL = -1,        /* invalid argument (null pointer, bad size or value)        */
+  RLF_ENOMEM = -2,        /* device or host allocation failed                          */
+  RLF_EDEVICE = -3,       /* a HIP runtime call failed; rlf_last_error() has its text  */
+  RLF_ERANGE = -4,        /* a facet would exceed the supported size (half-size 2^15)  */
+  RLF_EUNSUPPORTED = -5   /* valid request this build does not implement               */
+} rlf_status;
+
+typedef enum { RLF_FP64 = 0, RLF_MIXED = 1 } rlf_precision;
+
+/* Per-source result flags (rlf_fit_out.flags). */
+enum {
+  RLF_FLAG_BAD_VAR = 1,   /* sigma(e1) or sigma(e2) <= bad_sigma, or sqrt(det C) <= bad_sqrtdet (Sec. 4.1) */
+  RLF_FLAG_EMPTY = 2,     /* facet holds no visibility with positive weight; outputs are NaN               */
+  RLF_FLAG_EDGE = 4,      /* maximum on the edge of the evaluated ellipticity region                       */
+  RLF_FLAG_FALLBACK = 8   /* narrowed grid rejected; the full grid was evaluated instead                   */
+};
+
+/* rlf_model_vis modes. */
+enum {
+  RLF_MODEL_WRITE = 0,      /* out  = sum over sources                        */
+  RLF_MODEL_ACCUMULATE = 1, /* out += sum over sources                        */
+  RLF_MODEL_RESIDUAL = 2    /* out  = obs->vis - sum over sources (may alias) */
+};
+
+/* Algorithm parameters.  Defaults (rlf_params_default) are the paper's:
+ * beta = -0.7 (Eq. 1), ADD = -0.93 and ESP = 0.33 (Eq. 4), K = PSF_NAT = 38
+ * (Sec. 4.1), R_STD = 0.3136 (Sec. 2.4), [RMIN, RMAX] = [0.3, 3.5] arcsec
+ * (Sec. 4.2), 5 % likelihood threshold (Sec. 2.4), bad-fit thresholds 5e-3
+ * and 5e-5 (Sec. 4.1); num_r = 20 knots quadratic in the index, an 81 x 81
+ * ellipticity grid of step 0.02, FP64. */
+typedef struct {
+  double beta;            /* spectral index of Eq. 1                                   */
+  double ref_freq_hz;     /* reference frequency of the catalogue fluxes               */
+  double K;               /* facet field of view = K * scale length                    */
+  double add, esp;        /* Eq. 4 coefficients (prior median of the scale length)     */
+  double r_std;           /* width of the log-normal scale prior, in ln(alpha)          */
+  double rmin_arcsec;     /* scale-length marginalisation interval                      */
+  double rmax_arcsec;
+  int32_t num_r;          /* knots, 2..32; alpha_k = rmin + (rmax-rmin) (k/(num_r-1))^2  */
+  int32_t n_e;            /* ellipticity grid points per axis, odd, 3..255              */
+  double e_step;          /* grid step; 1/e_step must be an integer; e = (i-(n_e-1)/2) e_step */
+  double frac_thresh;     /* samples with L >= frac_thresh * Lmax enter the moments     */
+  double bad_sigma;       /* bad-fit thresholds                                         */
+  double bad_sqrtdet;
+  int32_t precision;      /* rlf_precision                                              */
+  int32_t reserved;       /* must be 0                                                  */
+} rlf_params;
+
+/* Observation, structure of arrays.  uvw are in metres in the phase-tracking
+ * frame; they are scaled to wavelengths at each channel centre
+ * (Sec. 2.2) as u = u_m * (freq / c). */
+typedef struct {
+  int64_t n_rows;              /* > 0                                                   */
+  int32_t n_chan;              /* 1..64                                                 */
+  int32_t reserved;            /* must be 0                                             */
+  const double *u_m, *v_m, *w_m; /* device [n_rows]                                     */
+  const double *freq_hz_host;  /* host [n_chan] channel centres, > 0                    */
+  const void *vis;             /* device [n_rows*n_chan] complex128 (FP64) or complex64 (MIXED) */
+  const void *weight;          /* device [n_rows*n_chan] f64 (FP64) or f32 (MIXED); w <= 0 = flagged */
+} rlf_obs;
+
+/* Source catalogue, structure of arrays, host memory.  Catalogue order is the
+ * processing order (Sec. 2.1: decreasing SNR or flux). */
+typedef struct {
+  int64_t n_src;                 /* > 0                                                */
+  const double *l, *m;           /* direction cosines, l^2 + m^2 < 1                   */
+  const double *flux_jy;         /* integrated flux at ref_freq_hz, finite             */
+  const double *alpha_arcsec;    /* scale length, finite, > 0 (rlf_alpha_from_flux when unknown) */
+  const double *e1, *e2;         /* sky-model shape, |e| < 1 (0 = circular start, Sec. 2.2) */
+  const double *prior_mu;        /* optional [n_src] ln(alpha_median/arcsec) of the scale prior;
+                                    NULL = Eq. 4 from flux_jy                           */
+} rlf_catalog;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int rlf_version(void);
+
+/* Fill *p with the defaults listed above.  Returns RLF_EINVAL if p is NULL. */
+int rlf_params_default(rlf_params *p);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t passed as void*; NULL = the legacy default stream).
+ * Validates *p (RLF_EINVAL), builds the ellipticity and knot tables and
+ * uploads them; synchronises.  *ctx is set only on success. */
+int rlf_create(rlf_ctx **ctx, int device, void *hip_stream, const rlf_params *p);
+
+/* Release a context and its tables (NULL is a no-op).  Facet objects made on
+ * it must be freed first. */
+int rlf_destroy(rlf_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int rlf_set_stream(rlf_ctx *ctx, void *hip_stream);
+
+/* Wait for all work enqueued by this context. */
+int rlf_sync(rlf_ctx *ctx);
+
+/* Text of the last error on ctx ("" if none).  Valid until the next call on ctx. */
+const char *rlf_last_error(const rlf_ctx *ctx);
+
+/* Eq. 4 (Sec. 2.2): alpha = exp(add + esp * ln(flux / 1 uJy)) arcsec, on the
+ * host for n fluxes (> 0). */
+int rlf_alpha_from_flux(const double *flux_jy_host, int64_t n, double add, double esp,
+                        double *alpha_arcsec_host);
+
+/* Sky model (Sec. 2.2): for every visibility, the sum over catalogue sources
+ * src_begin <= s < src_end of Eq. 1 at (u, v, w) in wavelengths,
+ * (nu/nu_ref)^beta S exp(2 pi i (u l + v m + w (sqrt(1-l^2-m^2)-1)))
+ *     / (1 + 4 pi^2 alpha^2 |A^{-T} (u,v)|^2)^{3/2},
+ * with A from Eq. 2 and the catalogue's (e1, e2).  `out` is device
+ * [n_rows*n_chan] in the context's complex type; see the mode enum.
+ * obs->vis is read only in RLF_MODEL_RESIDUAL and may then alias out. */
+int rlf_model_vis(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
+                  int64_t src_begin, int64_t src_end, void *out, int mode);
+
+/* Facet geometry for a catalogue on an observation (Sec. 2.3): per source
+ * theta_s = K * alpha_s (alpha in radians, converted first), cell size
+ * 1/theta_s, cells centred on the uv origin, half-size
+ * N_s = max over visibilities of |rint(u theta_s)|, |rint(v theta_s)|.
+ * Allocates the device accumulators and the compacted facet arrays, and the
+ * per-source scale-prior table (Sec. 2.4).  Synchronises (it reads the
+ * largest |u|, |v| back).  RLF_ERANGE if some N_s > 32767. */
+int rlf_facets_create(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
+                      rlf_facets **out);
+
+/* Extraction (Sec. 2.3) of every catalogue source into its facet.  For each
+ * source s and visibility with weight w > 0:
+ *   z = residual * exp(-2 pi i phi_s) + spec * S_s * profile_s(u, v)
+ * where residual = vis - sky (all sources, e.g. rlf_model_vis in
+ * RLF_MODEL_RESIDUAL mode), phi_s the Eq. 1 phase of source s, and the added
+ * term is its own model (real after the shift); then, in cell
+ * (rint(u theta_s), rint(v theta_s)) (round half to even):
+ *   count += 1, W += w, Z += w z.
+ * Compaction keeps the cells with count > 0 sorted by (iy, ix) and sets
+ * Vbar = Z / W.  `residual` is device, same type and shape as obs->vis.
+ * The catalogue must have the same sources and sizes as at
+ * rlf_facets_create (RLF_EINVAL otherwise); its shapes may differ.
+ * Integer results (cells, counts) are exact; FP sums are accumulated
+ * atomically, so their last bits may vary from run to run. */
+int rlf_extract_facets(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
+                       const void *residual, rlf_facets *facets);
+
+/* Sizes of a facet object: sources, non-empty cells of the last extraction
+ * (synchronises), and allocated dense cells.  Any output pointer may be NULL. */
+int rlf_facets_info(rlf_ctx *ctx, const rlf_facets *facets, int64_t *n_src,
+                    int64_t *n_cells_total, int64_t *n_dense_cells);
+
+/* Copy the last extraction to host memory (synchronises).  offsets
+ * [n_src+1] (CSR into the cell arrays), ix, iy, count [n_cells_total],
+ * wsum [n_cells_total], vbar [2*n_cells_total] (re, im), theta [n_src]
+ * radians.  Any output pointer may be NULL. */
+int rlf_facets_copy(rlf_ctx *ctx, const rlf_facets *facets, int64_t *offsets, int32_t *ix,
+                    int32_t *iy, int32_t *count, double *wsum, double *vbar, double *theta);
+
+/* Free a facet object (NULL is a no-op).  Synchronises its context's stream. */
+int rlf_facets_free(rlf_facets *facets);
+
+/* Fit options. */
+typedef struct {
+  int32_t mode;            /* 0 = full grid; 1 = windowed (window must be set)              */
+  int32_t want_surface;    /* nonzero: write out->surface                                    */
+  const int32_t *window;   /* device [n_src*4] inclusive (i1lo, i1hi, i2lo, i2hi) grid boxes */
+  int32_t fallback;        /* windowed mode: nonzero = refit on the full grid every source
+                              whose maximum lies on a window edge that is not the domain edge */
+  int32_t reserved;        /* must be 0 */
+} rlf_fit_opts;
+
+/* Fit outputs, device arrays [n_src] (surface [n_src*n_e*n_e]).  Any pointer
+ * may be NULL to skip that output except flags. */
+typedef struct {
+  double *e1, *e2;         /* likelihood-weighted mean over samples above threshold        */
+  double *s1, *s2, *c12;   /* standard deviations and covariance of those samples          */
+  double *lmax;            /* maximum of ln L(e) (shape-free constants omitted)            */
+  int32_t *argmax;         /* flat grid index i1*n_e + i2 of the maximum (smallest on ties) */
+  int32_t *n_above;        /* samples in the thresholded set                                */
+  uint32_t *flags;         /* RLF_FLAG_* (required)                                          */
+  double *surface;         /* ln L(e) on the full grid, i1 (e1) slow, -inf outside the
+                              evaluated region; f64 in both precision forms                 */
+} rlf_fit_out;
+
+/* Shape fit (Sec. 2.4) of every source of the last extraction.  For each
+ * source, evaluated grid point e (|e| < 1, inside the window if any) and
+ * knot alpha_k:
+ *   f_c = (1 + 4 pi^2 alpha_k^2 |A_e^{-T} k_c|^2)^{-3/2} at cell centres k_c,
+ *   D = sum_c W_c f_c Re Vbar_c,  Mm = sum_c W_c f_c^2,
+ *   ln L(e, alpha_k) = D^2 / (2 Mm) - ln(Mm) / 2        (flux marginalised)
+ *   ln L(e) = ln sum_k w_{s,k} L(e, alpha_k)              (scale marginalised)
+ * with w_{s,k} the natural-cubic-spline quadrature weight of knot k times the
+ * log-normal prior density at alpha_k.  Then Lmax, the set
+ * {ln L >= ln Lmax + ln frac}, its likelihood-weighted mean and covariance,
+ * and the flags. */
+int rlf_fit_sources(rlf_ctx *ctx, const rlf_facets *facets, const rlf_fit_opts *opts,
+                    rlf_fit_out *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLF_H */

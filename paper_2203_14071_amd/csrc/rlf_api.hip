@@ -1,0 +1,754 @@
+// Host runtime behind the C ABI of include/rlf.h: argument validation,
+// per-source and per-channel constant tables, facet sizing and buffers,
+// kernel launches on the context's stream, HIP-error mapping.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rlf.h"
+#include "rlf_internal.h"
+
+using namespace rlf;
+
+namespace {
+
+constexpr double kArcsec = M_PI / 648000.0;     // radians per arcsecond
+constexpr double kC = 299792458.0;              // m/s
+constexpr int kVersion = 100;                   // 0.1.0
+constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
+
+}  // namespace
+
+struct rlf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rlf_params p{};
+  std::string err;
+  // ellipticity grid
+  int n_valid = 0;
+  int half_r2 = 0;
+  int32_t *d_epts = nullptr;
+  // scale-length knots
+  std::vector<double> knots, ck;
+  double *d_sk = nullptr;
+  // channel table (cached by content)
+  std::vector<double> chan_key;
+  ChanTable *d_chan = nullptr;
+  // source tables of rlf_model_vis (two slots, reused by content)
+  struct Slot {
+    std::vector<double> key;
+    SrcModel *d = nullptr;
+    int64_t cap = 0;
+    uint64_t used = 0;
+  } slot[2];
+  uint64_t tick = 0;
+  uint32_t *d_err = nullptr;
+  double *d_absmax = nullptr;
+};
+
+struct rlf_facets {
+  rlf_ctx *ctx = nullptr;
+  int64_t n_src = 0;
+  int64_t dense_total = 0;
+  int mixed = 0;
+  std::vector<double> alpha;                 // catalogue sizes at creation
+  std::vector<double> theta;
+  std::vector<double> model_key;             // shapes of the uploaded model table
+  std::vector<SrcGeom> geom;
+  SrcModel *d_src = nullptr;
+  SrcGeom *d_geom = nullptr;
+  DenseAcc acc{};
+  Cells cells{};
+  double *d_logw = nullptr;
+  double *d_lsurf = nullptr;
+  int32_t *d_redo = nullptr;
+};
+
+namespace {
+
+int fail(rlf_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(rlf_ctx *c, hipError_t e, const char *what) {
+  return fail(c, RLF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                              \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+template <class T>
+int dalloc(rlf_ctx *c, T **p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, RLF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return RLF_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int validate_params(const rlf_params *p, std::string &why) {
+  if (!p) return why = "params is NULL", RLF_EINVAL;
+  if (!is_fin(p->beta) || !(p->ref_freq_hz > 0) || !is_fin(p->ref_freq_hz)) return why = "beta/ref_freq_hz", RLF_EINVAL;
+  if (!(p->K > 0) || !is_fin(p->K)) return why = "K must be > 0", RLF_EINVAL;
+  if (!is_fin(p->add) || !is_fin(p->esp) || !(p->r_std > 0) || !is_fin(p->r_std)) return why = "add/esp/r_std", RLF_EINVAL;
+  if (!(p->rmin_arcsec > 0) || !(p->rmax_arcsec > p->rmin_arcsec) || !is_fin(p->rmax_arcsec))
+    return why = "need 0 < rmin < rmax", RLF_EINVAL;
+  if (p->num_r < 2 || p->num_r > kMaxKnots) return why = "num_r must be in [2, 32]", RLF_EINVAL;
+  if (p->n_e < 3 || p->n_e > 255 || (p->n_e % 2) == 0) return why = "n_e must be odd, in [3, 255]", RLF_EINVAL;
+  if (!(p->e_step > 0) || !is_fin(p->e_step)) return why = "e_step must be > 0", RLF_EINVAL;
+  const double R = std::nearbyint(1.0 / p->e_step);
+  if (R < 1 || std::fabs(R * p->e_step - 1.0) > 1e-9) return why = "1/e_step must be an integer", RLF_EINVAL;
+  if (!(p->frac_thresh > 0) || !(p->frac_thresh <= 1)) return why = "frac_thresh must be in (0, 1]", RLF_EINVAL;
+  if (!is_fin(p->bad_sigma) || !is_fin(p->bad_sqrtdet)) return why = "bad thresholds", RLF_EINVAL;
+  if (p->precision != RLF_FP64 && p->precision != RLF_MIXED) return why = "precision", RLF_EINVAL;
+  if (p->reserved != 0) return why = "reserved must be 0", RLF_EINVAL;
+  return RLF_OK;
+}
+
+// Natural cubic spline through (x_k, y_k): its exact integral over
+// [x_0, x_{n-1}] is linear in y; return the weights.  Second derivatives M
+// solve h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1} = 6 (d_i - d_{i-1})
+// (d_i the slope on interval i, M_0 = M_{n-1} = 0, Thomas algorithm), and each
+// interval contributes h (y_i + y_{i+1}) / 2 - h^3 (M_i + M_{i+1}) / 24.
+std::vector<double> spline_weights(const std::vector<double> &x) {
+  const int n = (int)x.size();
+  std::vector<double> h(n - 1), w(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) h[i] = x[i + 1] - x[i];
+  for (int k = 0; k < n; ++k) {
+    std::vector<double> y(n, 0.0), M(n, 0.0);
+    y[k] = 1.0;
+    const int m = n - 2;
+    if (m > 0) {
+      std::vector<double> a(m), b(m), c(m), r(m);
+      for (int t = 0; t < m; ++t) {
+        const int i = t + 1;
+        a[t] = h[i - 1];
+        b[t] = 2.0 * (h[i - 1] + h[i]);
+        c[t] = h[i];
+        r[t] = 6.0 * ((y[i + 1] - y[i]) / h[i] - (y[i] - y[i - 1]) / h[i - 1]);
+      }
+      for (int t = 1; t < m; ++t) {
+        const double f = a[t] / b[t - 1];
+        b[t] -= f * c[t - 1];
+        r[t] -= f * r[t - 1];
+      }
+      M[m] = r[m - 1] / b[m - 1];
+      for (int t = m - 2; t >= 0; --t) M[t + 1] = (r[t] - c[t] * M[t + 2]) / b[t];
+    }
+    double integral = 0.0;
+    for (int i = 0; i + 1 < n; ++i)
+      integral += h[i] * (y[i] + y[i + 1]) / 2.0 - h[i] * h[i] * h[i] * (M[i] + M[i + 1]) / 24.0;
+    w[k] = integral;
+  }
+  return w;
+}
+
+int check_obs(rlf_ctx *c, const rlf_obs *o) {
+  if (!o) return fail(c, RLF_EINVAL, "obs is NULL");
+  if (o->n_rows <= 0) return fail(c, RLF_EINVAL, "obs.n_rows must be > 0");
+  if (o->n_chan < 1 || o->n_chan > kMaxChan) return fail(c, RLF_EINVAL, "obs.n_chan must be in [1, 64]");
+  if (o->reserved != 0) return fail(c, RLF_EINVAL, "obs.reserved must be 0");
+  if (!o->u_m || !o->v_m || !o->w_m || !o->freq_hz_host || !o->weight)
+    return fail(c, RLF_EINVAL, "obs: NULL array");
+  if (o->n_rows > ((int64_t)1 << 40) / o->n_chan) return fail(c, RLF_EINVAL, "obs too large");
+  for (int k = 0; k < o->n_chan; ++k)
+    if (!(o->freq_hz_host[k] > 0) || !is_fin(o->freq_hz_host[k]))
+      return fail(c, RLF_EINVAL, "obs.freq_hz_host must be finite and > 0");
+  return RLF_OK;
+}
+
+int check_cat(rlf_ctx *c, const rlf_catalog *k, bool need_prior_flux) {
+  if (!k) return fail(c, RLF_EINVAL, "catalog is NULL");
+  if (k->n_src <= 0 || k->n_src > (1 << 24)) return fail(c, RLF_EINVAL, "catalog.n_src must be in [1, 2^24]");
+  if (!k->l || !k->m || !k->flux_jy || !k->alpha_arcsec || !k->e1 || !k->e2)
+    return fail(c, RLF_EINVAL, "catalog: NULL array");
+  for (int64_t s = 0; s < k->n_src; ++s) {
+    const double l = k->l[s], m = k->m[s], e1 = k->e1[s], e2 = k->e2[s];
+    if (!is_fin(l) || !is_fin(m) || !(l * l + m * m < 1.0)) return fail(c, RLF_EINVAL, "catalog: need l^2+m^2 < 1");
+    if (!is_fin(k->flux_jy[s])) return fail(c, RLF_EINVAL, "catalog: flux must be finite");
+    if (need_prior_flux && !k->prior_mu && !(k->flux_jy[s] > 0))
+      return fail(c, RLF_EINVAL, "catalog: flux must be > 0 for the Eq. 4 prior (or give prior_mu)");
+    if (!(k->alpha_arcsec[s] > 0) || !is_fin(k->alpha_arcsec[s])) return fail(c, RLF_EINVAL, "catalog: alpha must be finite and > 0");
+    if (!is_fin(e1) || !is_fin(e2) || !(e1 * e1 + e2 * e2 < 1.0)) return fail(c, RLF_EINVAL, "catalog: need |e| < 1");
+    if (k->prior_mu && !is_fin(k->prior_mu[s])) return fail(c, RLF_EINVAL, "catalog: prior_mu must be finite");
+  }
+  return RLF_OK;
+}
+
+SrcModel pack_source(const rlf_params &p, const rlf_catalog *k, int64_t s) {
+  SrcModel r{};
+  const double l = k->l[s], m = k->m[s];
+  const double r2 = l * l + m * m;
+  r.l = l;
+  r.m = m;
+  r.n1 = -r2 / (1.0 + std::sqrt(1.0 - r2));
+  r.flux = k->flux_jy[s];
+  const double e1 = k->e1[s], e2 = k->e2[s];
+  const double det = 1.0 - e1 * e1 - e2 * e2;
+  const double a11 = (1.0 + e1) / det, a12 = e2 / det, a22 = (1.0 - e1) / det;
+  const double ar = k->alpha_arcsec[s] * kArcsec;
+  const double cst = 4.0 * M_PI * M_PI * ar * ar;
+  r.q11 = cst * (a11 * a11 + a12 * a12);
+  r.q12x2 = 2.0 * cst * a12 * (a11 + a22);
+  r.q22 = cst * (a12 * a12 + a22 * a22);
+  r.theta = p.K * (k->alpha_arcsec[s] * kArcsec);
+  return r;
+}
+
+std::vector<double> cat_key(const rlf_catalog *k) {
+  std::vector<double> key;
+  key.reserve((size_t)k->n_src * 6);
+  const double *arr[6] = {k->l, k->m, k->flux_jy, k->alpha_arcsec, k->e1, k->e2};
+  for (int a = 0; a < 6; ++a) key.insert(key.end(), arr[a], arr[a] + k->n_src);
+  return key;
+}
+
+int upload_sources(rlf_ctx *c, const rlf_catalog *k, SrcModel *dst) {
+  std::vector<SrcModel> h((size_t)k->n_src);
+  for (int64_t s = 0; s < k->n_src; ++s) h[(size_t)s] = pack_source(c->p, k, s);
+  HIPCHK(c, hipStreamSynchronize(c->stream));      // no pending kernel may still read dst
+  HIPCHK(c, hipMemcpy(dst, h.data(), sizeof(SrcModel) * h.size(), hipMemcpyHostToDevice));
+  return RLF_OK;
+}
+
+// Device source table for rlf_model_vis, reused while the catalogue content is unchanged.
+int model_table(rlf_ctx *c, const rlf_catalog *k, const SrcModel **out) {
+  std::vector<double> key = cat_key(k);
+  ++c->tick;
+  for (auto &sl : c->slot)
+    if (sl.d && sl.key == key) {
+      sl.used = c->tick;
+      *out = sl.d;
+      return RLF_OK;
+    }
+  auto &sl = c->slot[0].used <= c->slot[1].used ? c->slot[0] : c->slot[1];
+  if (sl.cap < k->n_src) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(sl.d);
+    sl.cap = 0;
+    if (int e = dalloc(c, &sl.d, k->n_src)) return e;
+    sl.cap = k->n_src;
+  }
+  if (int e = upload_sources(c, k, sl.d)) return e;
+  sl.key.swap(key);
+  sl.used = c->tick;
+  *out = sl.d;
+  return RLF_OK;
+}
+
+int chan_table(rlf_ctx *c, const rlf_obs *o) {
+  std::vector<double> key(o->freq_hz_host, o->freq_hz_host + o->n_chan);
+  if (c->d_chan && key == c->chan_key) return RLF_OK;
+  ChanTable h{};
+  for (int k = 0; k < o->n_chan; ++k) {
+    h.scale[k] = o->freq_hz_host[k] / kC;
+    h.spec[k] = std::pow(o->freq_hz_host[k] / c->p.ref_freq_hz, c->p.beta);
+  }
+  if (!c->d_chan)
+    if (int e = dalloc(c, &c->d_chan, 1)) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->d_chan, &h, sizeof(h), hipMemcpyHostToDevice));
+  c->chan_key.swap(key);
+  return RLF_OK;
+}
+
+int set_device(rlf_ctx *c) {
+  HIPCHK(c, hipSetDevice(c->device));
+  return RLF_OK;
+}
+
+void free_facets(rlf_facets *f) {
+  dfree(f->d_src);
+  dfree(f->d_geom);
+  dfree(f->acc.count);
+  dfree(f->acc.wsum);
+  dfree(f->acc.zre);
+  dfree(f->acc.zim);
+  dfree(f->cells.offsets);
+  dfree(f->cells.n_nonempty);
+  dfree(f->cells.ix);
+  dfree(f->cells.iy);
+  dfree(f->cells.count);
+  dfree(f->cells.wsum);
+  dfree(f->cells.vre);
+  dfree(f->cells.vim);
+  dfree(f->cells.fit64);
+  dfree(f->cells.fit32);
+  dfree(f->d_logw);
+  dfree(f->d_lsurf);
+  dfree(f->d_redo);
+}
+
+int check_device_error(rlf_ctx *c) {
+  uint32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost));
+  if (e) {
+    uint32_t z = 0;
+    HIPCHK(c, hipMemcpy(c->d_err, &z, sizeof(z), hipMemcpyHostToDevice));
+    return fail(c, RLF_ERANGE, "a visibility fell outside its facet: the observation's uvw changed after rlf_facets_create");
+  }
+  return RLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlf_version(void) { return kVersion; }
+
+int rlf_params_default(rlf_params *p) {
+  if (!p) return RLF_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->beta = -0.7;
+  p->ref_freq_hz = 1.4e9;
+  p->K = 38.0;
+  p->add = -0.93;
+  p->esp = 0.33;
+  p->r_std = 0.3136;
+  p->rmin_arcsec = 0.3;
+  p->rmax_arcsec = 3.5;
+  p->num_r = 20;
+  p->n_e = 81;
+  p->e_step = 0.02;
+  p->frac_thresh = 0.05;
+  p->bad_sigma = 5e-3;
+  p->bad_sqrtdet = 5e-5;
+  p->precision = RLF_FP64;
+  p->reserved = 0;
+  return RLF_OK;
+}
+
+int rlf_create(rlf_ctx **out, int device, void *hip_stream, const rlf_params *p) {
+  if (!out) return RLF_EINVAL;
+  std::string why;
+  if (validate_params(p, why) != RLF_OK) return RLF_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return device < 0 ? RLF_EINVAL : RLF_EDEVICE;
+  }
+  rlf_ctx *c = new (std::nothrow) rlf_ctx();
+  if (!c) return RLF_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->p = *p;
+  int rc = RLF_OK;
+  do {
+    if ((rc = set_device(c))) break;
+    // ellipticity grid: valid points (|e| < 1 on the integers), increasing flat index
+    const int R = (int)std::nearbyint(1.0 / p->e_step);
+    const int ctr = (p->n_e - 1) / 2;
+    c->half_r2 = R * R;
+    std::vector<int32_t> ep;
+    for (int i1 = 0; i1 < p->n_e; ++i1)
+      for (int i2 = 0; i2 < p->n_e; ++i2)
+        if ((i1 - ctr) * (i1 - ctr) + (i2 - ctr) * (i2 - ctr) < c->half_r2) ep.push_back(i1 * p->n_e + i2);
+    c->n_valid = (int)ep.size();
+    if ((rc = dalloc(c, &c->d_epts, c->n_valid))) break;
+    if (hipMemcpy(c->d_epts, ep.data(), sizeof(int32_t) * ep.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = RLF_EDEVICE;
+      break;
+    }
+    // knots alpha_k = rmin + (rmax - rmin) (k / (n-1))^2 and s_k = 4 pi^2 alpha_k^2
+    c->knots.resize(p->num_r);
+    std::vector<double> sk(p->num_r);
+    for (int k = 0; k < p->num_r; ++k) {
+      const double t = (double)k / (double)(p->num_r - 1);
+      c->knots[k] = p->rmin_arcsec + (p->rmax_arcsec - p->rmin_arcsec) * t * t;
+      const double ar = c->knots[k] * kArcsec;
+      sk[k] = 4.0 * M_PI * M_PI * ar * ar;
+    }
+    c->ck = spline_weights(c->knots);
+    if ((rc = dalloc(c, &c->d_sk, p->num_r))) break;
+    if (hipMemcpy(c->d_sk, sk.data(), sizeof(double) * sk.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = RLF_EDEVICE;
+      break;
+    }
+    if ((rc = dalloc(c, &c->d_err, 1))) break;
+    if ((rc = dalloc(c, &c->d_absmax, 2))) break;
+    if (hipMemset(c->d_err, 0, sizeof(uint32_t)) != hipSuccess) {
+      rc = RLF_EDEVICE;
+      break;
+    }
+  } while (0);
+  if (rc != RLF_OK) {
+    rlf_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return RLF_OK;
+}
+
+int rlf_destroy(rlf_ctx *c) {
+  if (!c) return RLF_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  dfree(c->d_epts);
+  dfree(c->d_sk);
+  dfree(c->d_chan);
+  dfree(c->d_err);
+  dfree(c->d_absmax);
+  for (auto &sl : c->slot) dfree(sl.d);
+  delete c;
+  return RLF_OK;
+}
+
+int rlf_set_stream(rlf_ctx *c, void *hip_stream) {
+  if (!c) return RLF_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return RLF_OK;
+}
+
+int rlf_sync(rlf_ctx *c) {
+  if (!c) return RLF_EINVAL;
+  if (int e = set_device(c)) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_device_error(c);
+}
+
+const char *rlf_last_error(const rlf_ctx *c) { return c ? c->err.c_str() : "context is NULL"; }
+
+int rlf_alpha_from_flux(const double *flux, int64_t n, double add, double esp, double *alpha) {
+  if (!flux || !alpha || n <= 0 || !is_fin(add) || !is_fin(esp)) return RLF_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(flux[i] > 0) || !is_fin(flux[i])) return RLF_EINVAL;
+  for (int64_t i = 0; i < n; ++i) alpha[i] = std::exp(add + esp * std::log(flux[i] * 1e6));
+  return RLF_OK;
+}
+
+int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_t src_begin,
+                  int64_t src_end, void *out, int mode) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (int e = check_obs(c, obs)) return e;
+  if (int e = check_cat(c, cat, false)) return e;
+  if (!out) return fail(c, RLF_EINVAL, "out is NULL");
+  if (mode < 0 || mode > 2) return fail(c, RLF_EINVAL, "mode");
+  if (mode == RLF_MODEL_RESIDUAL && !obs->vis) return fail(c, RLF_EINVAL, "obs.vis is NULL");
+  if (src_begin < 0 || src_end > cat->n_src || src_begin > src_end) return fail(c, RLF_EINVAL, "source range");
+  if (int e = set_device(c)) return e;
+  if (int e = chan_table(c, obs)) return e;
+  const SrcModel *d_src = nullptr;
+  if (int e = model_table(c, cat, &d_src)) return e;
+  ModelArgs a{};
+  a.u_m = obs->u_m;
+  a.v_m = obs->v_m;
+  a.w_m = obs->w_m;
+  a.n_rows = obs->n_rows;
+  a.n_chan = obs->n_chan;
+  a.mode = mode;
+  a.chan = c->d_chan;
+  a.src = d_src;
+  a.s_begin = (int32_t)src_begin;
+  a.s_end = (int32_t)src_end;
+  a.vis_in = obs->vis;
+  a.out = out;
+  hipError_t e = c->p.precision == RLF_MIXED ? launch_model_mixed(a, c->stream) : launch_model_f64(a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "model kernel launch");
+  return RLF_OK;
+}
+
+int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets **out) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!out) return fail(c, RLF_EINVAL, "out is NULL");
+  if (int e = check_obs(c, obs)) return e;
+  if (int e = check_cat(c, cat, true)) return e;
+  if (int e = set_device(c)) return e;
+  // largest |u|, |v| (metres) bound every cell index
+  HIPCHK(c, hipMemsetAsync(c->d_absmax, 0, 2 * sizeof(double), c->stream));
+  HIPCHK(c, launch_absmax(obs->u_m, obs->n_rows, c->d_absmax, 0, c->stream));
+  HIPCHK(c, launch_absmax(obs->v_m, obs->n_rows, c->d_absmax, 1, c->stream));
+  double mx[2] = {0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(mx, c->d_absmax, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!is_fin(mx[0]) || !is_fin(mx[1])) return fail(c, RLF_EINVAL, "obs: non-finite u or v");
+
+  rlf_facets *f = new (std::nothrow) rlf_facets();
+  if (!f) return fail(c, RLF_ENOMEM, "host allocation");
+  f->ctx = c;
+  f->n_src = cat->n_src;
+  f->mixed = c->p.precision == RLF_MIXED;
+  f->alpha.assign(cat->alpha_arcsec, cat->alpha_arcsec + cat->n_src);
+  f->theta.resize((size_t)cat->n_src);
+  f->geom.resize((size_t)cat->n_src);
+  int64_t total = 0;
+  for (int64_t s = 0; s < cat->n_src; ++s) {
+    const double th = c->p.K * (cat->alpha_arcsec[s] * kArcsec);
+    int64_t half = 0;
+    for (int k = 0; k < obs->n_chan; ++k) {
+      const double sc = obs->freq_hz_host[k] / kC;
+      const double tu = std::nearbyint((mx[0] * sc) * th), tv = std::nearbyint((mx[1] * sc) * th);
+      const double t = tu > tv ? tu : tv;
+      if (!(t <= (double)kMaxFacetHalf)) {
+        delete f;
+        return fail(c, RLF_ERANGE, "facet half-size exceeds 16383 cells (alpha * K too large for the uv extent)");
+      }
+      half = (int64_t)t > half ? (int64_t)t : half;
+    }
+    f->theta[(size_t)s] = th;
+    f->geom[(size_t)s].base = total;
+    f->geom[(size_t)s].half = (int32_t)half;
+    f->geom[(size_t)s].side = (int32_t)(2 * half + 1);
+    total += (2 * half + 1) * (2 * half + 1);
+  }
+  f->dense_total = total;
+  // scale-marginalisation weights: ln(c_k) + ln p_s(alpha_k), log-normal prior
+  const int R = c->p.num_r;
+  std::vector<double> logw((size_t)cat->n_src * R);
+  for (int64_t s = 0; s < cat->n_src; ++s) {
+    const double mu = cat->prior_mu ? cat->prior_mu[s] : c->p.add + c->p.esp * std::log(cat->flux_jy[s] * 1e6);
+    for (int k = 0; k < R; ++k) {
+      const double a = c->knots[k];
+      const double z = std::log(a) - mu;
+      const double lp = -z * z / (2.0 * c->p.r_std * c->p.r_std) - std::log(a * c->p.r_std * std::sqrt(2.0 * M_PI));
+      logw[(size_t)s * R + k] = std::log(c->ck[k]) + lp;
+    }
+  }
+  int rc = RLF_OK;
+  do {
+    if ((rc = dalloc(c, &f->d_src, f->n_src))) break;
+    if ((rc = dalloc(c, &f->d_geom, f->n_src))) break;
+    if ((rc = dalloc(c, &f->acc.count, total))) break;
+    if ((rc = dalloc(c, &f->acc.wsum, total))) break;
+    if ((rc = dalloc(c, &f->acc.zre, total))) break;
+    if ((rc = dalloc(c, &f->acc.zim, total))) break;
+    if ((rc = dalloc(c, &f->cells.offsets, f->n_src + 1))) break;
+    if ((rc = dalloc(c, &f->cells.n_nonempty, f->n_src))) break;
+    if ((rc = dalloc(c, &f->cells.ix, total))) break;
+    if ((rc = dalloc(c, &f->cells.iy, total))) break;
+    if ((rc = dalloc(c, &f->cells.count, total))) break;
+    if ((rc = dalloc(c, &f->cells.wsum, total))) break;
+    if ((rc = dalloc(c, &f->cells.vre, total))) break;
+    if ((rc = dalloc(c, &f->cells.vim, total))) break;
+    if (f->mixed) {
+      if ((rc = dalloc(c, &f->cells.fit32, total))) break;
+    } else {
+      if ((rc = dalloc(c, &f->cells.fit64, total))) break;
+    }
+    if ((rc = dalloc(c, &f->d_logw, f->n_src * R))) break;
+    if ((rc = dalloc(c, &f->d_lsurf, f->n_src * (int64_t)c->n_valid))) break;
+    if ((rc = dalloc(c, &f->d_redo, f->n_src))) break;
+  } while (0);
+  if (rc != RLF_OK) {
+    free_facets(f);
+    delete f;
+    return rc;
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(f->d_geom, f->geom.data(), sizeof(SrcGeom) * f->geom.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(f->acc.count, 0, sizeof(uint32_t) * (size_t)total);
+  if (e == hipSuccess) e = hipMemset(f->acc.wsum, 0, sizeof(double) * (size_t)total);
+  if (e == hipSuccess) e = hipMemset(f->acc.zre, 0, sizeof(double) * (size_t)total);
+  if (e == hipSuccess) e = hipMemset(f->acc.zim, 0, sizeof(double) * (size_t)total);
+  if (e == hipSuccess) e = hipMemset(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1));
+  if (e == hipSuccess) e = hipMemset(f->d_redo, 0, sizeof(int32_t) * (size_t)f->n_src);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_facets(f);
+    delete f;
+    return hip_fail(c, e, "facet buffer initialisation");
+  }
+  if (int r = upload_sources(c, cat, f->d_src)) {
+    free_facets(f);
+    delete f;
+    return r;
+  }
+  f->model_key = cat_key(cat);
+  *out = f;
+  return RLF_OK;
+}
+
+int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *residual,
+                       rlf_facets *f) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
+  if (!residual) return fail(c, RLF_EINVAL, "residual is NULL");
+  if (int e = check_obs(c, obs)) return e;
+  if (int e = check_cat(c, cat, false)) return e;
+  if (cat->n_src != f->n_src || std::memcmp(cat->alpha_arcsec, f->alpha.data(), sizeof(double) * f->n_src) != 0)
+    return fail(c, RLF_EINVAL, "catalogue sources/sizes differ from rlf_facets_create");
+  if (int e = set_device(c)) return e;
+  if (int e = chan_table(c, obs)) return e;
+  std::vector<double> key = cat_key(cat);
+  if (key != f->model_key) {
+    if (int e = upload_sources(c, cat, f->d_src)) return e;
+    f->model_key.swap(key);
+  }
+  ExtractArgs a{};
+  a.u_m = obs->u_m;
+  a.v_m = obs->v_m;
+  a.w_m = obs->w_m;
+  a.n_rows = obs->n_rows;
+  a.n_chan = obs->n_chan;
+  a.n_src = (int32_t)f->n_src;
+  a.chan = c->d_chan;
+  a.src = f->d_src;
+  a.geom = f->d_geom;
+  a.resid = residual;
+  a.weight = obs->weight;
+  a.acc = f->acc;
+  a.err = c->d_err;
+  hipError_t e = f->mixed ? launch_extract_mixed(a, c->stream) : launch_extract_f64(a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "extract kernel launch");
+  CompactArgs ca{};
+  ca.n_src = (int32_t)f->n_src;
+  ca.geom = f->d_geom;
+  ca.src = f->d_src;
+  ca.acc = f->acc;
+  ca.cells = f->cells;
+  e = launch_compact(ca, f->mixed, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "compact kernel launch");
+  return RLF_OK;
+}
+
+int rlf_facets_info(rlf_ctx *c, const rlf_facets *f, int64_t *n_src, int64_t *n_cells, int64_t *n_dense) {
+  if (!c) return RLF_EINVAL;
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets");
+  if (n_src) *n_src = f->n_src;
+  if (n_dense) *n_dense = f->dense_total;
+  if (n_cells) {
+    if (int e = set_device(c)) return e;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(n_cells, f->cells.offsets + f->n_src, sizeof(int64_t), hipMemcpyDeviceToHost));
+    return check_device_error(c);
+  }
+  return RLF_OK;
+}
+
+int rlf_facets_copy(rlf_ctx *c, const rlf_facets *f, int64_t *offsets, int32_t *ix, int32_t *iy,
+                    int32_t *count, double *wsum, double *vbar, double *theta) {
+  if (!c) return RLF_EINVAL;
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets");
+  if (int e = set_device(c)) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (int e = check_device_error(c)) return e;
+  int64_t n = 0;
+  HIPCHK(c, hipMemcpy(&n, f->cells.offsets + f->n_src, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (offsets) HIPCHK(c, hipMemcpy(offsets, f->cells.offsets, sizeof(int64_t) * (f->n_src + 1), hipMemcpyDeviceToHost));
+  if (ix) HIPCHK(c, hipMemcpy(ix, f->cells.ix, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (iy) HIPCHK(c, hipMemcpy(iy, f->cells.iy, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (count) HIPCHK(c, hipMemcpy(count, f->cells.count, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (wsum) HIPCHK(c, hipMemcpy(wsum, f->cells.wsum, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (vbar) {
+    std::vector<double> re((size_t)n), im((size_t)n);
+    HIPCHK(c, hipMemcpy(re.data(), f->cells.vre, sizeof(double) * n, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(im.data(), f->cells.vim, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < n; ++k) {
+      vbar[2 * k] = re[(size_t)k];
+      vbar[2 * k + 1] = im[(size_t)k];
+    }
+  }
+  if (theta) std::memcpy(theta, f->theta.data(), sizeof(double) * f->n_src);
+  return RLF_OK;
+}
+
+int rlf_facets_free(rlf_facets *f) {
+  if (!f) return RLF_OK;
+  rlf_ctx *c = f->ctx;
+  if (c) {
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+  }
+  free_facets(f);
+  delete f;
+  return RLF_OK;
+}
+
+int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, rlf_fit_out *out) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
+  if (!out || !out->flags) return fail(c, RLF_EINVAL, "out/out.flags is NULL");
+  rlf_fit_opts o{};
+  if (opts) o = *opts;
+  if (o.reserved != 0) return fail(c, RLF_EINVAL, "opts.reserved must be 0");
+  if (o.mode != 0 && o.mode != 1) return fail(c, RLF_EINVAL, "opts.mode");
+  if (o.mode == 1 && !o.window) return fail(c, RLF_EINVAL, "windowed mode needs opts.window");
+  if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
+  if (int e = set_device(c)) return e;
+  const bool windowed = o.mode == 1;
+  FitArgs fa{};
+  fa.n_src = (int32_t)f->n_src;
+  fa.n_valid = c->n_valid;
+  fa.n_e = c->p.n_e;
+  fa.num_r = c->p.num_r;
+  fa.e_step = c->p.e_step;
+  fa.epts = c->d_epts;
+  fa.sk = c->d_sk;
+  fa.logw = f->d_logw;
+  fa.offsets = f->cells.offsets;
+  fa.fit64 = f->cells.fit64;
+  fa.fit32 = f->cells.fit32;
+  fa.window = windowed ? o.window : nullptr;
+  fa.redo = nullptr;
+  fa.lsurf = f->d_lsurf;
+  EstimateArgs ea{};
+  ea.n_src = (int32_t)f->n_src;
+  ea.n_valid = c->n_valid;
+  ea.n_e = c->p.n_e;
+  ea.half_r2 = c->half_r2;
+  ea.e_step = c->p.e_step;
+  ea.log_frac = std::log(c->p.frac_thresh);
+  ea.bad_sigma = c->p.bad_sigma;
+  ea.bad_sqrtdet = c->p.bad_sqrtdet;
+  ea.epts = c->d_epts;
+  ea.offsets = f->cells.offsets;
+  ea.lsurf = f->d_lsurf;
+  ea.window = fa.window;
+  ea.redo = nullptr;
+  ea.redo_out = (windowed && o.fallback) ? f->d_redo : nullptr;
+  ea.e1 = out->e1;
+  ea.e2 = out->e2;
+  ea.s1 = out->s1;
+  ea.s2 = out->s2;
+  ea.c12 = out->c12;
+  ea.lmax = out->lmax;
+  ea.argmax = out->argmax;
+  ea.n_above = out->n_above;
+  ea.flags = out->flags;
+  ea.surface = o.want_surface ? out->surface : nullptr;
+  hipError_t e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "fit kernel launch");
+  e = launch_estimate(ea, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "estimate kernel launch");
+  if (windowed && o.fallback) {
+    fa.window = nullptr;
+    fa.redo = f->d_redo;
+    ea.window = nullptr;
+    ea.redo = f->d_redo;
+    ea.redo_out = nullptr;
+    e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fit kernel launch (fallback)");
+    e = launch_estimate(ea, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "estimate kernel launch (fallback)");
+  }
+  return RLF_OK;
+}
+
+}  // extern "C"

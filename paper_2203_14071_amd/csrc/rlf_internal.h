@@ -1,0 +1,139 @@
+// Internal types shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rlf.h"
+
+namespace rlf {
+
+constexpr int kMaxChan = 64;
+constexpr int kMaxKnots = 32;
+constexpr int kMaxHalf = 32767;
+
+// Per-source constants of the visibility model (Eq. 1), packed so one
+// 64-byte scalar load brings a source into SGPRs: every lane of a wave works
+// on the same source at the same time.
+struct alignas(64) SrcModel {
+  double l, m, n1;           // direction cosines; n1 = sqrt(1-l^2-m^2)-1
+  double flux;               // S at the reference frequency
+  double q11, q12x2, q22;    // 4 pi^2 alpha^2 |A^{-T} k|^2 = q11 u^2 + q12x2 u v + q22 v^2
+  double theta;              // facet field of view (radians); cell index = rint(u theta)
+};
+
+// Per-source facet geometry: dense accumulator block [side*side], cells
+// centred on the uv origin, index (iy+half)*side + (ix+half).
+struct SrcGeom {
+  int64_t base;              // offset of the source's dense block
+  int32_t half;              // N_s
+  int32_t side;              // 2 N_s + 1
+};
+
+// Per-channel constants (device table).
+struct ChanTable {
+  double scale[kMaxChan];    // nu_c / c: metres -> wavelengths
+  double spec[kMaxChan];     // (nu_c / nu_ref)^beta
+};
+
+// Dense accumulators of one extraction.
+struct DenseAcc {
+  uint32_t *count;
+  double *wsum, *zre, *zim;
+};
+
+// Compacted facets (CSR by source, cells sorted by (iy, ix)).
+struct Cells {
+  int64_t *offsets;          // [n_src+1]
+  int64_t *n_nonempty;       // [n_src]
+  int32_t *ix, *iy, *count;
+  double *wsum, *vre, *vim;
+  double4 *fit64;            // (uc, vc, W, W Re Vbar) for the FP64 fit
+  float4 *fit32;             // same in FP32 for the mixed fit
+};
+
+struct ModelArgs {
+  const double *u_m, *v_m, *w_m;
+  int64_t n_rows;
+  int32_t n_chan;
+  int32_t mode;
+  const ChanTable *chan;
+  const SrcModel *src;
+  int32_t s_begin, s_end;
+  const void *vis_in;        // RESIDUAL mode only
+  void *out;
+};
+
+struct ExtractArgs {
+  const double *u_m, *v_m, *w_m;
+  int64_t n_rows;
+  int32_t n_chan;
+  int32_t n_src;
+  const ChanTable *chan;
+  const SrcModel *src;
+  const SrcGeom *geom;
+  const void *resid;
+  const void *weight;
+  DenseAcc acc;
+  uint32_t *err;             // bit 0: a cell index fell outside its facet (visibility skipped)
+};
+
+struct CompactArgs {
+  int32_t n_src;
+  const SrcGeom *geom;
+  const SrcModel *src;
+  DenseAcc acc;
+  Cells cells;
+};
+
+struct FitArgs {
+  int32_t n_src;
+  int32_t n_valid;           // valid grid points (|e| < 1)
+  int32_t n_e;
+  int32_t num_r;
+  double e_step;
+  const int32_t *epts;       // [n_valid] flat grid indices, increasing
+  const double *sk;          // [num_r] 4 pi^2 alpha_k^2 (radians)
+  const double *logw;        // [n_src*num_r] ln(spline weight * prior density)
+  const int64_t *offsets;
+  const double4 *fit64;
+  const float4 *fit32;
+  const int32_t *window;     // [n_src*4] or null
+  const int32_t *redo;       // fallback pass: [n_src] nonzero = evaluate; null = all
+  double *lsurf;             // [n_src*n_valid] ln L(e); -inf where not evaluated
+};
+
+struct EstimateArgs {
+  int32_t n_src;
+  int32_t n_valid;
+  int32_t n_e;
+  int32_t half_r2;           // (1/e_step)^2 for the |e| < 1 test
+  double e_step;
+  double log_frac;
+  double bad_sigma, bad_sqrtdet;
+  const int32_t *epts;
+  const int64_t *offsets;
+  const double *lsurf;
+  const int32_t *window;     // null = full grid
+  const int32_t *redo;       // fallback pass: only these sources; null = all
+  int32_t *redo_out;         // windowed pass with fallback: set where the maximum is on an inner window edge
+  double *e1, *e2, *s1, *s2, *c12, *lmax;
+  int32_t *argmax, *n_above;
+  uint32_t *flags;
+  double *surface;           // [n_src*n_e*n_e] or null
+};
+
+// Launchers (enqueue on `st`; return the launch status).
+hipError_t launch_model_f64(const ModelArgs &a, hipStream_t st);
+hipError_t launch_model_mixed(const ModelArgs &a, hipStream_t st);
+hipError_t launch_extract_f64(const ExtractArgs &a, hipStream_t st);
+hipError_t launch_extract_mixed(const ExtractArgs &a, hipStream_t st);
+hipError_t launch_compact(const CompactArgs &a, int mixed, hipStream_t st);
+hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st);
+hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st);
+hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
+hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
+
+}  // namespace rlf

@@ -1,0 +1,184 @@
+"""GPU parity of the HIP path with the oracle, element by element, on the tiny
+workload (config 0: 20 antennas, 11,400 visibilities, 10 sources) and on
+small variants that exercise ragged tails, several source tiles, several
+channels, flagged data and empty facets.  Every call goes through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_14071_amd import rlf, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(cfg_index=0, cfg=None, n_src=None, seed_shift=0, freq=None):
+    cfg = synth.CONFIGS[cfg_index] if cfg is None else cfg
+    if freq is not None:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, freq_hz=tuple(freq))
+    o = synth.observation(cfg_index, cfg)
+    cat = synth.catalogue(cfg, synth.rng(cfg_index, synth.STREAM_CAT + seed_shift), n_src)
+    nz = synth.noise(cfg, synth.rng(cfg_index, synth.STREAM_NOISE + seed_shift), o.n_rows * o.n_chan)
+    data = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat) + nz
+    return cfg, o, cat, data
+
+
+def _run_all(o, cat, data, ctx, p=oracle.Params(), prior_mu=None):
+    """GPU: residual against the circular sky model, extraction, fit."""
+    torch = G.torch_cuda()
+    catc = G.circular(cat)
+    obs = G.make_obs(o, data)
+    resid = torch.empty_like(obs.vis)
+    ctx.model_vis(obs, catc, resid, mode=rlf.RLF_MODEL_RESIDUAL)
+    f = ctx.facets_create(obs, catc, prior_mu=prior_mu)
+    ctx.extract_facets(obs, catc, resid, f, prior_mu=prior_mu)
+    out = G.fit_out_tensors(cat.n_src)
+    ctx.fit_sources(f, out, want_surface=True)
+    ctx.sync()
+    return resid.cpu().numpy(), f.copy(), G.host(out), f
+
+
+def _oracle_all(o, cat, data, p=oracle.Params(), mu=None):
+    catc = G.circular(cat)
+    resid = data - oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, catc, p.ref_freq_hz, p.beta)
+    facets = [G.oracle_facet(o, resid, catc, s, p) for s in range(cat.n_src)]
+    fits = [oracle.fit_source(facets[s], cat.flux_jy[s], p, None if mu is None else mu[s])
+            for s in range(cat.n_src)]
+    return resid, facets, fits
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return rlf.Context(0)
+
+
+def test_model_vis_matches_oracle_cfg0(ctx):
+    torch = G.torch_cuda()
+    cfg, o, cat, data = _field(0)
+    obs = G.make_obs(o, data)
+    out = torch.empty_like(obs.vis)
+    ctx.model_vis(obs, cat, out, mode=rlf.RLF_MODEL_WRITE)
+    ref = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat)
+    ctx.sync()
+    got = out.cpu().numpy()
+    bound = G.VIS_RTOL_L1 * np.sum(cat.flux_jy)
+    assert np.max(np.abs(got - ref)) <= bound
+    # accumulate mode adds onto what is there; a sub-range of sources sums to the whole
+    ctx.model_vis(obs, cat, out, mode=rlf.RLF_MODEL_WRITE, src_begin=0, src_end=4)
+    ctx.model_vis(obs, cat, out, mode=rlf.RLF_MODEL_ACCUMULATE, src_begin=4, src_end=cat.n_src)
+    ctx.sync()
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 2 * bound
+
+
+def test_full_path_matches_oracle_cfg0(ctx):
+    cfg, o, cat, data = _field(0)
+    resid_g, fac_g, out_g, f = _run_all(o, cat, data, ctx)
+    resid_o, fac_o, fits_o = _oracle_all(o, cat, data)
+    assert np.max(np.abs(resid_g - resid_o)) <= G.VIS_RTOL_L1 * np.sum(cat.flux_jy)
+    # the GPU facets come from the GPU residual, the oracle's from its own
+    scale = np.max(np.abs(resid_o))
+    for s in range(cat.n_src):
+        G.check_facet(fac_g, s, fac_o[s], scale, cat.flux_jy[s])
+    for s in range(cat.n_src):
+        surf_o, est_o = fits_o[s]
+        G.check_fit(out_g, s, surf_o, G.oracle_estimate_variants(surf_o), out_g["surface"][s])
+    # integer invariants of the gridding
+    for s in range(cat.n_src):
+        a, b = fac_g["offsets"][s], fac_g["offsets"][s + 1]
+        assert fac_g["count"][a:b].sum() == o.n_rows
+    f.free()
+
+
+def test_ragged_multichannel_many_sources(ctx):
+    """3 channels, 70 sources (three source tiles, ragged), 13 antennas x 37
+    samples (2,886 rows: ragged against 512-row wave chunks), flagged
+    visibilities, prior medians given per source."""
+    cfg = synth.small_config(0, n_ant=13, n_time=37, n_src=70)
+    freq = (1.2e9, 1.4e9, 1.55e9)
+    import dataclasses
+    cfg = dataclasses.replace(cfg, freq_hz=freq)
+    o = synth.observation(0, cfg)
+    cat = synth.catalogue(cfg, np.random.default_rng(21))
+    rng = np.random.default_rng(22)
+    n = o.n_rows * o.n_chan
+    o.weight = o.weight * rng.uniform(0.5, 1.5, n)
+    o.weight[rng.random(n) < 0.07] = 0.0
+    o.weight[rng.random(n) < 0.02] = -1.0
+    data = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat) + \
+        cfg.noise_sigma_jy * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    mu = rng.normal(0.0, 0.2, cat.n_src)
+    p = oracle.Params()
+    resid_g, fac_g, out_g, f = _run_all(o, cat, data, ctx, prior_mu=mu)
+    resid_o, fac_o, fits_o = _oracle_all(o, cat, data, mu=mu)
+    scale = np.max(np.abs(resid_o))
+    assert np.max(np.abs(resid_g - resid_o)) <= G.VIS_RTOL_L1 * np.sum(cat.flux_jy) * 2 ** 0.7
+    for s in range(cat.n_src):
+        G.check_facet(fac_g, s, fac_o[s], scale, cat.flux_jy[s] * 1.2)
+        a, b = fac_g["offsets"][s], fac_g["offsets"][s + 1]
+        assert fac_g["count"][a:b].sum() == np.count_nonzero(o.weight > 0)
+    for s in range(0, cat.n_src, 7):
+        surf_o, est_o = fits_o[s]
+        G.check_fit(out_g, s, surf_o, G.oracle_estimate_variants(surf_o), out_g["surface"][s])
+    f.free()
+
+
+def test_all_flagged_gives_empty_facets(ctx):
+    torch = G.torch_cuda()
+    cfg, o, cat, data = _field(0)
+    o.weight = np.zeros_like(o.weight)
+    obs = G.make_obs(o, data)
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    out = G.fit_out_tensors(cat.n_src)
+    ctx.fit_sources(f, out, want_surface=True)
+    ctx.sync()
+    h = G.host(out)
+    n_src, n_cells, _ = f.info()
+    assert n_cells == 0
+    assert np.all(h["flags"] == rlf.RLF_FLAG_EMPTY)
+    assert np.all(np.isnan(h["e1"])) and np.all(h["argmax"] == -1) and np.all(h["n_above"] == 0)
+    assert np.all(np.isneginf(h["surface"]))
+    f.free()
+
+
+def test_repeat_extraction_is_self_cleaning(ctx):
+    """A second extraction on the same facet object gives the same cells
+    (the compaction step clears the accumulators)."""
+    torch = G.torch_cuda()
+    cfg, o, cat, data = _field(0)
+    obs = G.make_obs(o, data)
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    a = f.copy()
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    b = f.copy()
+    for k in ("offsets", "ix", "iy", "count"):
+        assert np.array_equal(a[k], b[k])
+    assert np.allclose(a["vbar"], b["vbar"], rtol=1e-12, atol=1e-18)
+    f.free()
+
+
+def test_abi_errors_on_gpu(ctx):
+    torch = G.torch_cuda()
+    cfg, o, cat, data = _field(0)
+    obs = G.make_obs(o, data)
+    bad = cat.with_shape(np.full(cat.n_src, 0.9), np.full(cat.n_src, 0.5))      # |e| >= 1
+    with pytest.raises(rlf.RlfError) as e:
+        ctx.model_vis(obs, bad, torch.empty_like(obs.vis))
+    assert e.value.code == rlf.RLF_EINVAL
+    f = ctx.facets_create(obs, cat)
+    other = synth.Catalogue(cat.l, cat.m, cat.flux_jy, cat.alpha_arcsec * 1.01, cat.e1, cat.e2)
+    with pytest.raises(rlf.RlfError) as e:
+        ctx.extract_facets(obs, other, obs.vis, f)
+    assert e.value.code == rlf.RLF_EINVAL
+    big = synth.Catalogue(cat.l, cat.m, cat.flux_jy, np.full(cat.n_src, 3e4), cat.e1, cat.e2)
+    with pytest.raises(rlf.RlfError) as e:
+        ctx.facets_create(obs, big)
+    assert e.value.code == rlf.RLF_ERANGE
+    with pytest.raises(rlf.RlfError) as e:
+        ctx.model_vis(obs, cat, torch.empty_like(obs.vis), src_begin=3, src_end=99)
+    assert e.value.code == rlf.RLF_EINVAL
+    f.free()

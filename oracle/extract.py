@@ -73,13 +73,17 @@ def extract_facet(u_m, v_m, w_m, freq_hz, weight, residual, src, theta,
     if ix.size == 0:
         e = np.zeros(0, dtype=np.int64)
         return Facet(theta, e, e, e, np.zeros(0), np.zeros(0, np.complex128), np.zeros(0), np.zeros(0))
-    cells, inv = np.unique(np.stack([iy, ix], axis=1), axis=0, return_inverse=True)
+    # one integer key per (iy, ix) that sorts like the pair: iy major, ix minor
+    x0, span = ix.min(), ix.max() - ix.min() + 1
+    key = (iy - iy.min()) * span + (ix - x0)
+    ukey, inv = np.unique(key, return_inverse=True)
     inv = inv.reshape(-1)
     count = np.bincount(inv).astype(np.int64)
     wsum = np.bincount(inv, weights=wt)
     zre = np.bincount(inv, weights=wt * z.real)
     zim = np.bincount(inv, weights=wt * z.imag)
-    cy, cx = cells[:, 0].astype(np.int64), cells[:, 1].astype(np.int64)
+    cy = ukey // span + iy.min()
+    cx = ukey % span + x0
     return Facet(theta, cx, cy, count, wsum, (zre + 1j * zim) / wsum, cx / theta, cy / theta)
 
 

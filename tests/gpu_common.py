@@ -69,7 +69,9 @@ def check_facet(gpu, s, ref: oracle.Facet, resid_scale, flux):
     assert np.array_equal(gpu["ix"][a:b], ref.ix), s
     assert np.array_equal(gpu["iy"][a:b], ref.iy), s
     assert np.array_equal(gpu["count"][a:b], ref.count), s
-    assert np.allclose(gpu["wsum"][a:b], ref.wsum, rtol=1e-13, atol=0), s
+    # both sides sum the same positive weights in different orders: |dW| <= (n-1) u W
+    rtol = np.maximum(1e-15, 2.3e-16 * ref.count)
+    assert np.all(np.abs(gpu["wsum"][a:b] - ref.wsum) <= rtol * ref.wsum), s
     err = np.max(np.abs(gpu["vbar"][a:b] - ref.vbar)) if b > a else 0.0
     assert err <= VBAR_TOL * (resid_scale + flux), (s, err, resid_scale, flux)
     assert gpu["theta"][s] == ref.theta

@@ -1,0 +1,74 @@
+"""GPU parity at the benchmark's full size (SKA-MID-like field: 9,266,880
+visibilities, 1000 sources, FP64) with the launch configuration the benchmark
+times.  The oracle checks sampled outputs it can compute one by one; the
+rest is checked through invariants that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_14071_amd import rlf, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def field():
+    torch = G.torch_cuda()
+    cfg = synth.CONFIGS[1]
+    o = synth.observation(1)
+    cat = synth.catalogue(cfg, synth.rng(1, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(1, synth.STREAM_NOISE), o.n_rows)
+    obs = G.make_obs(o, nz)
+    ctx = rlf.Context(0)
+    return cfg, o, cat, nz, obs, ctx
+
+
+def test_sky_model_sampled_rows(field):
+    torch = G.torch_cuda()
+    cfg, o, cat, nz, obs, ctx = field
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([[0, 1, o.n_rows - 1], rng.integers(0, o.n_rows, 3000)]))
+    out = torch.empty_like(obs.vis)
+    ctx.model_vis(obs, cat, out, mode=rlf.RLF_MODEL_WRITE)
+    res = torch.empty_like(obs.vis)
+    catc = G.circular(cat)
+    ctx.model_vis(obs, catc, res, mode=rlf.RLF_MODEL_RESIDUAL)
+    ctx.sync()
+    got = out.cpu().numpy()[rows]
+    ref = oracle.sky_model(o.u_m[rows], o.v_m[rows], o.w_m[rows], o.freq_hz, cat)
+    bound = G.VIS_RTOL_L1 * np.sum(cat.flux_jy)
+    assert np.max(np.abs(got - ref)) <= bound
+    ref_r = nz[rows] - oracle.sky_model(o.u_m[rows], o.v_m[rows], o.w_m[rows], o.freq_hz, catc)
+    assert np.max(np.abs(res.cpu().numpy()[rows] - ref_r)) <= bound
+
+
+def test_extraction_and_fit_sampled_sources(field):
+    """Residual = the generator's noise (the exactly-subtracted field), own
+    models with the true shapes: every facet is its source plus noise."""
+    cfg, o, cat, nz, obs, ctx = field
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    out = G.fit_out_tensors(cat.n_src)
+    ctx.fit_sources(f, out, want_surface=True)
+    ctx.sync()
+    fac = f.copy()
+    h = G.host(out)
+    n_src, n_cells, n_dense = f.info()
+    # invariants over all 1000 sources
+    cnt = np.add.reduceat(fac["count"], fac["offsets"][:-1])
+    assert np.all(cnt == o.n_rows)
+    ws = np.add.reduceat(fac["wsum"], fac["offsets"][:-1])
+    assert np.allclose(ws, o.weight.sum(), rtol=1e-12)
+    assert np.all(np.diff(fac["offsets"]) > 0)
+    assert np.all(h["flags"] & rlf.RLF_FLAG_EMPTY == 0)
+    # sampled sources, element by element
+    a = cat.alpha_arcsec
+    pick = sorted({int(np.argmin(a)), int(np.argmax(a)), int(np.argsort(a)[len(a) // 2]), 137})
+    scale = np.max(np.abs(nz))
+    for s in pick:
+        ref = G.oracle_facet(o, nz, cat, s)
+        G.check_facet(fac, s, ref, scale, cat.flux_jy[s])
+        surf, est = oracle.fit_source(ref, cat.flux_jy[s])
+        G.check_fit(h, s, surf, G.oracle_estimate_variants(surf), h["surface"][s])
+    f.free()

@@ -49,7 +49,7 @@ typedef enum {
   RLF_EINVAL = -1,        /* invalid argument (null pointer, bad size or value)        */
   RLF_ENOMEM = -2,        /* device or host allocation failed                          */
   RLF_EDEVICE = -3,       /* a HIP runtime call failed; rlf_last_error() has its text  */
-  RLF_ERANGE = -4,        /* a facet would exceed the supported size (half-size 2^15)  */
+  RLF_ERANGE = -4,        /* a facet or the visibility count exceeds supported sizes  */
   RLF_EUNSUPPORTED = -5   /* valid request this build does not implement               */
 } rlf_status;
 
@@ -163,26 +163,30 @@ int rlf_model_vis(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
  * theta_s = K * alpha_s (alpha in radians, converted first), cell size
  * 1/theta_s, cells centred on the uv origin, half-size
  * N_s = max over visibilities of |rint(u theta_s)|, |rint(v theta_s)|.
- * Allocates the device accumulators and the compacted facet arrays, and the
- * per-source scale-prior table (Sec. 2.4).  Synchronises (it reads the
- * largest |u|, |v| back).  RLF_ERANGE if some N_s > 32767. */
+ * Allocates the device accumulators, the compacted facet arrays and the
+ * per-source scale-prior table (Sec. 2.4), and orders the visibilities once
+ * along a Morton curve over (u, v) (a layout for the extraction kernels; no
+ * result depends on it beyond FP summation order).  Synchronises.  The
+ * observation's uvw and sizes must not change while the object is used.
+ * RLF_ERANGE if some N_s > 16383 or there are 2^32 or more visibilities. */
 int rlf_facets_create(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
                       rlf_facets **out);
 
 /* Extraction (Sec. 2.3) of every catalogue source into its facet.  For each
  * source s and visibility with weight w > 0:
  *   z = residual * exp(-2 pi i phi_s) + spec * S_s * profile_s(u, v)
- * where residual = vis - sky (all sources, e.g. rlf_model_vis in
- * RLF_MODEL_RESIDUAL mode), phi_s the Eq. 1 phase of source s, and the added
- * term is its own model (real after the shift); then, in cell
+ * where residual = vis - sky (all sources), phi_s the Eq. 1 phase of source s,
+ * and the added term is its own model (real after the shift); then, in cell
  * (rint(u theta_s), rint(v theta_s)) (round half to even):
  *   count += 1, W += w, Z += w z.
  * Compaction keeps the cells with count > 0 sorted by (iy, ix) and sets
- * Vbar = Z / W.  `residual` is device, same type and shape as obs->vis.
- * The catalogue must have the same sources and sizes as at
- * rlf_facets_create (RLF_EINVAL otherwise); its shapes may differ.
- * Integer results (cells, counts) are exact; FP sums are accumulated
- * atomically, so their last bits may vary from run to run. */
+ * Vbar = Z / W.  `residual` is device, same type and shape as obs->vis
+ * (e.g. rlf_model_vis in RLF_MODEL_RESIDUAL mode); NULL means "compute it":
+ * the library subtracts the sky model of this catalogue (all sources, their
+ * current shapes) from obs->vis itself.  The catalogue must have the same
+ * sources and sizes as at rlf_facets_create (RLF_EINVAL otherwise); its
+ * shapes may differ.  Integer results (cells, counts) are exact; FP sums are
+ * accumulated atomically, so their last bits may vary from run to run. */
 int rlf_extract_facets(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
                        const void *residual, rlf_facets *facets);
 

@@ -2,31 +2,37 @@
 // residual to the source, add back the source's own model, and accumulate the
 // weighted result into the source's facet cell (rint(u theta), rint(v theta)).
 //
-// Work decomposition.  A wave owns 64*VPT consecutive rows of one channel
-// (lane L: rows [L*VPT, (L+1)*VPT)) and a tile of sources; grid.y tiles the
-// sources.  Rows are baseline-major with time fastest, so a lane's rows trace
-// a short arc of one baseline and usually stay in one facet cell: the lane
-// accumulates its rows serially in registers and flushes only when the cell
-// changes.  At the end of its rows the wave merges equal cells of adjacent
-// lanes with a segmented shuffle reduction, and one lane per run of equal
-// cells issues the global atomics.  Integer counts are exact; FP sums are
-// atomic (order-dependent in the last bits).
+// Work decomposition.  Lanes are sources: a wave holds 64 sources (one per
+// lane, their constants in VGPRs) and walks a chunk of visibilities in the
+// facet object's uv-sorted order; each visibility's data is uniform across
+// the wave and arrives through scalar loads.  Along the sorted order every
+// source stays in one facet cell for long runs, so each lane accumulates
+// (count, W, Z) in registers and issues global atomics only when its cell
+// changes or the chunk ends: no cross-lane merging is needed.
+//
+// XCD-aware launch: blocks are dispatched round-robin over the 8 XCDs; the
+// grid is laid out so that all blocks of one visibility chunk (all source
+// tiles) land on one XCD and share its L2 for the chunk's data.
+//
+// Integer results are exact (cell index in FP64 exactly as rint(fl(u theta)));
+// FP sums are atomic and order-dependent in their last bits.
+#include "rlf_devmath.h"
 #include "rlf_internal.h"
 
 namespace rlf {
 
 namespace {
 
-constexpr int kVPT = 8;               // rows per lane
-constexpr int kSrcTile = 32;          // sources per block (grid.y tiles the catalogue)
+constexpr int kXcd = 8;
+constexpr int kWaves = 4;          // waves (source tiles) per block
 
-struct Partial {
-  int key;                            // dense cell index in the source's block, -1 = none
+struct Run {
+  int key;                         // cell in the source's dense block, -1 = none
   uint32_t n;
   double w, zr, zi;
 };
 
-__device__ __forceinline__ void flush_atomic(const DenseAcc &acc, int64_t base, const Partial &p) {
+__device__ __forceinline__ void flush(const DenseAcc &acc, int64_t base, const Run &p) {
   const int64_t k = base + p.key;
   atomicAdd(acc.count + k, p.n);
   unsafeAtomicAdd(acc.wsum + k, p.w);
@@ -34,114 +40,115 @@ __device__ __forceinline__ void flush_atomic(const DenseAcc &acc, int64_t base, 
   unsafeAtomicAdd(acc.zim + k, p.zi);
 }
 
-// Merge each run of equal keys across the wave (keys of adjacent lanes) and
-// flush one partial per run.
-__device__ __forceinline__ void wave_flush(const DenseAcc &acc, int64_t base, Partial p) {
-  const int lane = __lane_id();
-  const int prev = __shfl_up(p.key, 1);
-  const bool head = (lane == 0) || (prev != p.key);
-  const uint64_t heads = __ballot(head);
-  const int seg = __popcll(heads & ((2ull << lane) - 1ull));
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int seg_o = __shfl_down(seg, d);
-    const uint32_t n_o = __shfl_down(p.n, d);
-    const double w_o = __shfl_down(p.w, d);
-    const double zr_o = __shfl_down(p.zr, d);
-    const double zi_o = __shfl_down(p.zi, d);
-    if (lane + d < 64 && seg_o == seg) {
-      p.n += n_o;
-      p.w += w_o;
-      p.zr += zr_o;
-      p.zi += zi_o;
-    }
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+  __shared__ double2 tab[kCisTable + 1];
+  if (!kMixed) {
+    cis_table_init(tab);
+    __syncthreads();
   }
-  if (head && p.key >= 0) flush_atomic(acc, base, p);
-}
-
-__global__ __launch_bounds__(256) void k_extract_f64(ExtractArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int c = (int)(gwave % a.n_chan);
-  const int64_t chunk = gwave / a.n_chan;
-  const int64_t row0 = chunk * (64 * kVPT) + (int64_t)lane * kVPT;
-  if (chunk * (64 * kVPT) >= a.n_rows) return;           // whole wave past the end
+  const int wid = threadIdx.x >> 6;
+  const int bpc = (a.n_tiles + kWaves - 1) / kWaves;           // blocks per chunk
+  const int64_t xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+  const int64_t chunk = (local / bpc) * kXcd + xcd;
+  const int tile = (int)(local % bpc) * kWaves + wid;
+  if (chunk >= a.n_chunks || tile >= a.n_tiles) return;          // uniform per wave
 
-  const double sc = a.chan->scale[c];
-  const double spec = a.chan->spec[c];
-  const double2 *__restrict__ resid = reinterpret_cast<const double2 *>(a.resid);
-  const double *__restrict__ wt = reinterpret_cast<const double *>(a.weight);
+  const int s_raw = tile * 64 + lane;
+  const bool active = s_raw < a.n_src;
+  const int s = active ? s_raw : a.n_src - 1;
+  const SrcGeom g = a.geom[s];
+  const double theta = a.src[s].theta;
+  const int64_t j0 = chunk * (int64_t)a.chunk;
+  const int64_t j1 = min(a.sv.n_vis, j0 + (int64_t)a.chunk);
+  const double spec0 = a.chan->spec[0];
 
-  double u[kVPT], v[kVPT], w[kVPT], rr[kVPT], ri[kVPT], ww[kVPT];
-#pragma unroll
-  for (int j = 0; j < kVPT; ++j) {
-    const int64_t row = row0 + j;
-    if (row < a.n_rows) {
-      const int64_t vi = row * a.n_chan + c;
-      u[j] = __dmul_rn(a.u_m[row], sc);
-      v[j] = __dmul_rn(a.v_m[row], sc);
-      w[j] = __dmul_rn(a.w_m[row], sc);
-      const double2 r = resid[vi];
-      rr[j] = r.x;
-      ri[j] = r.y;
-      ww[j] = wt[vi];
-    } else {
-      u[j] = v[j] = w[j] = rr[j] = ri[j] = 0.0;
-      ww[j] = 0.0;                                         // skipped like a flagged visibility
-    }
-  }
-
-  const int s_begin = blockIdx.y * kSrcTile;
-  const int s_end = min(a.n_src, s_begin + kSrcTile);
-  for (int s = s_begin; s < s_end; ++s) {
+  Run cur{-1, 0u, 0.0, 0.0, 0.0};
+  if (!kMixed) {
     const SrcModel p = a.src[s];
-    const SrcGeom g = a.geom[s];
-    const double amp = spec * p.flux;
-    Partial cur{-1, 0u, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < kVPT; ++j) {
-      if (!(ww[j] > 0.0)) continue;
-      const double ph = fma(u[j], p.l, fma(v[j], p.m, w[j] * p.n1));
-      double sn, cs;
-      sincospi(ph + ph, &sn, &cs);
-      // residual * exp(-2 pi i ph)
-      double zr = fma(rr[j], cs, ri[j] * sn);
-      const double zi = fma(ri[j], cs, -(rr[j] * sn));
-      // own model, real after the shift
-      const double x = fma(p.q11, u[j] * u[j], fma(p.q12x2, u[j] * v[j], fma(p.q22, v[j] * v[j], 1.0)));
-      const double r = rsqrt(x);
-      zr = fma(amp, r * r * r, zr);
-      const int ix = (int)rint(__dmul_rn(u[j], p.theta));
-      const int iy = (int)rint(__dmul_rn(v[j], p.theta));
+    const double2 *__restrict__ res = reinterpret_cast<const double2 *>(a.sv.res);
+    const double *__restrict__ wt = reinterpret_cast<const double *>(a.sv.wt);
+    for (int64_t j = j0; j < j1; ++j) {
+      const double ww = wt[j];
+      if (!(ww > 0.0)) continue;                                   // uniform
+      const double u = a.sv.u[j], v = a.sv.v[j], w = a.sv.w[j];
+      const double2 r = res[j];
+      const double spec = a.n_chan > 1 ? a.chan->spec[a.sv.chan[j]] : spec0;
+      const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
+      const double2 cs = cis2pi_f64(ph, tab);
+      double zr = fma(r.x, cs.x, r.y * cs.y);                      // residual * exp(-2 pi i ph)
+      const double zi = fma(r.y, cs.x, -(r.x * cs.y));
+      const double x = fma(p.q11, u * u, fma(p.q12x2, u * v, fma(p.q22, v * v, 1.0)));
+      const double q = rsqrt_f64(x);
+      zr = fma(spec * p.flux, q * q * q, zr);                      // own model, real after the shift
+      const int ix = (int)rint(__dmul_rn(u, theta));
+      const int iy = (int)rint(__dmul_rn(v, theta));
       const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
-      if (ox >= (unsigned)g.side || oy >= (unsigned)g.side) {
-        atomicOr(a.err, 1u);
-        continue;
-      }
-      const int key = (int)oy * g.side + (int)ox;
+      const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
+      const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
       if (key != cur.key) {
-        if (cur.key >= 0) flush_atomic(a.acc, g.base, cur);
+        if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
+        if (!inb && active) atomicOr(a.err, 1u);
         cur.key = key;
         cur.n = 0u;
         cur.w = cur.zr = cur.zi = 0.0;
       }
       cur.n += 1u;
-      cur.w += ww[j];
-      cur.zr = fma(ww[j], zr, cur.zr);
-      cur.zi = fma(ww[j], zi, cur.zi);
+      cur.w += ww;
+      cur.zr = fma(ww, zr, cur.zr);
+      cur.zi = fma(ww, zi, cur.zi);
     }
-    wave_flush(a.acc, g.base, cur);
+  } else {
+    const SrcMixed p = a.src32[s];
+    const float2 *__restrict__ res = reinterpret_cast<const float2 *>(a.sv.res);
+    const float *__restrict__ wt = reinterpret_cast<const float *>(a.sv.wt);
+    for (int64_t j = j0; j < j1; ++j) {
+      const float ww = wt[j];
+      if (!(ww > 0.0f)) continue;                                  // uniform
+      const double u = a.sv.u[j], v = a.sv.v[j], w = a.sv.w[j];
+      const float2 r = res[j];
+      const float spec = (float)(a.n_chan > 1 ? a.chan->spec[a.sv.chan[j]] : spec0);
+      const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
+      const float t = (float)(ph - rint(ph));                      // turns, |t| <= 1/2
+      const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
+      float zr = fmaf(r.x, cs, r.y * sn);
+      const float zi = fmaf(r.y, cs, -(r.x * sn));
+      const float uf = (float)u, vf = (float)v;
+      const float x = fmaf(p.q11, uf * uf, fmaf(p.q12x2, uf * vf, fmaf(p.q22, vf * vf, 1.0f)));
+      const float q = __builtin_amdgcn_rsqf(x);
+      zr = fmaf(spec * p.flux, q * q * q, zr);
+      const int ix = (int)rint(__dmul_rn(u, theta));
+      const int iy = (int)rint(__dmul_rn(v, theta));
+      const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
+      const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
+      const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
+      if (key != cur.key) {
+        if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
+        if (!inb && active) atomicOr(a.err, 1u);
+        cur.key = key;
+        cur.n = 0u;
+        cur.w = cur.zr = cur.zi = 0.0;
+      }
+      const double wd = (double)ww;
+      cur.n += 1u;
+      cur.w += wd;
+      cur.zr = fma(wd, (double)zr, cur.zr);
+      cur.zi = fma(wd, (double)zi, cur.zi);
+    }
   }
+  if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
 }
 
 }  // namespace
 
-hipError_t launch_extract_f64(const ExtractArgs &a, hipStream_t st) {
-  const int64_t rows_per_wave = 64 * kVPT;
-  const int64_t waves = ((a.n_rows + rows_per_wave - 1) / rows_per_wave) * a.n_chan;
-  const int64_t blocks = (waves + 3) / 4;
-  const int tiles = (a.n_src + kSrcTile - 1) / kSrcTile;
-  hipLaunchKernelGGL(k_extract_f64, dim3((unsigned)blocks, (unsigned)tiles), dim3(256), 0, st, a);
+hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st) {
+  const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
+  const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
+  if (mixed)
+    hipLaunchKernelGGL(k_extract<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_extract<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a);
   return hipGetLastError();
 }
 

@@ -1,23 +1,66 @@
 // Sky-model DFT (Sec. 2.2, Eq. 1): every visibility accumulates the model of
-// every catalogue source in [s_begin, s_end).
+// every catalogue source.
 //
-// One thread per visibility; the source loop is uniform across the wave, so
-// the 64-byte source record comes in through one scalar load and feeds all
-// 64 lanes from SGPRs.  The work per (visibility, source) pair is the FP64
-// phase (3 FMA), sincospi of that phase, the quadratic form of the sheared
-// profile (3 FMA), x^{-3/2} through rsqrt, and two FMAs into the sum.
+// One thread per visibility and a uniform loop over sources: the source
+// record comes in through scalar loads shared by the wave.  Work per
+// (visibility, source) pair:
+//   FP64 form:  phase (3 FMA), exp(2 pi i phase) by exact reduction + LDS
+//               table + short polynomials (~19 ops), profile
+//               (3 FMA + rsqrt + 2 MUL), 2 FMA into the sum;
+//   mixed form: phase and its reduction to [-1/2, 1/2] turns in FP64, then
+//               v_sin/v_cos (argument in turns), profile and sum in FP32.
+// Two entry kernels: visibilities in caller order (rlf_model_vis), and the
+// residual in the facet object's uv-sorted order (extraction input).
+#include "rlf_devmath.h"
 #include "rlf_internal.h"
 
 namespace rlf {
 
 namespace {
 
-__device__ __forceinline__ double shape_factor(double x) {
-  const double r = rsqrt(x);
-  return r * r * r;
+__device__ __forceinline__ double2 sum_f64(double u, double v, double w, const SrcModel *__restrict__ src, int b,
+                                           int e, const double2 *tab) {
+  const double uu = u * u, uv = u * v, vv = v * v;
+  double ar = 0.0, ai = 0.0;
+  for (int s = b; s < e; ++s) {
+    const SrcModel p = src[s];
+    const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
+    const double2 cs = cis2pi_f64(ph, tab);
+    const double x = fma(p.q11, uu, fma(p.q12x2, uv, fma(p.q22, vv, 1.0)));
+    const double r = rsqrt_f64(x);
+    const double amp = p.flux * (r * r * r);
+    ar = fma(amp, cs.x, ar);
+    ai = fma(amp, cs.y, ai);
+  }
+  return make_double2(ar, ai);
 }
 
-__global__ __launch_bounds__(256) void k_model_f64(ModelArgs a) {
+__device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const SrcMixed *__restrict__ src, int b,
+                                            int e) {
+  const float uf = (float)u, vf = (float)v;
+  const float uu = uf * uf, uv = uf * vf, vv = vf * vf;
+  float ar = 0.0f, ai = 0.0f;
+  for (int s = b; s < e; ++s) {
+    const SrcMixed p = src[s];
+    const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
+    const float t = (float)(ph - rint(ph));                 // turns, |t| <= 1/2
+    const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
+    const float x = fmaf(p.q11, uu, fmaf(p.q12x2, uv, fmaf(p.q22, vv, 1.0f)));
+    const float r = __builtin_amdgcn_rsqf(x);
+    const float amp = p.flux * (r * r * r);
+    ar = fmaf(amp, cs, ar);
+    ai = fmaf(amp, sn, ai);
+  }
+  return make_float2(ar, ai);
+}
+
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_model(ModelArgs a) {
+  __shared__ double2 tab[kCisTable + 1];
+  if (!kMixed) {
+    cis_table_init(tab);
+    __syncthreads();
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n_vis = a.n_rows * a.n_chan;
   if (i >= n_vis) return;
@@ -31,40 +74,89 @@ __global__ __launch_bounds__(256) void k_model_f64(ModelArgs a) {
   const double u = __dmul_rn(a.u_m[row], sc);
   const double v = __dmul_rn(a.v_m[row], sc);
   const double w = __dmul_rn(a.w_m[row], sc);
-  const double uu = u * u, uv = u * v, vv = v * v;
-  double acc_r = 0.0, acc_i = 0.0;
-  const SrcModel *__restrict__ src = a.src;
-  for (int s = a.s_begin; s < a.s_end; ++s) {
-    const SrcModel p = src[s];
-    const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
-    double sn, cs;
-    sincospi(ph + ph, &sn, &cs);
-    const double x = fma(p.q11, uu, fma(p.q12x2, uv, fma(p.q22, vv, 1.0)));
-    const double amp = p.flux * shape_factor(x);
-    acc_r = fma(amp, cs, acc_r);
-    acc_i = fma(amp, sn, acc_i);
-  }
   const double spec = a.chan->spec[c];
-  double2 *out = reinterpret_cast<double2 *>(a.out);
-  double2 r;
-  if (a.mode == 0) {
-    r = make_double2(spec * acc_r, spec * acc_i);
-  } else if (a.mode == 1) {
-    const double2 o = out[i];
-    r = make_double2(fma(spec, acc_r, o.x), fma(spec, acc_i, o.y));
+  if (!kMixed) {
+    const double2 acc = sum_f64(u, v, w, a.src, a.s_begin, a.s_end, tab);
+    double2 *out = reinterpret_cast<double2 *>(a.out);
+    double2 r;
+    if (a.mode == 0) {
+      r = make_double2(spec * acc.x, spec * acc.y);
+    } else if (a.mode == 1) {
+      const double2 o = out[i];
+      r = make_double2(fma(spec, acc.x, o.x), fma(spec, acc.y, o.y));
+    } else {
+      const double2 o = reinterpret_cast<const double2 *>(a.vis_in)[i];
+      r = make_double2(fma(-spec, acc.x, o.x), fma(-spec, acc.y, o.y));
+    }
+    out[i] = r;
   } else {
-    const double2 o = reinterpret_cast<const double2 *>(a.vis_in)[i];
-    r = make_double2(fma(-spec, acc_r, o.x), fma(-spec, acc_i, o.y));
+    const float2 acc = sum_mixed(u, v, w, a.src32, a.s_begin, a.s_end);
+    const float sp = (float)spec;
+    float2 *out = reinterpret_cast<float2 *>(a.out);
+    float2 r;
+    if (a.mode == 0) {
+      r = make_float2(sp * acc.x, sp * acc.y);
+    } else if (a.mode == 1) {
+      const float2 o = out[i];
+      r = make_float2(fmaf(sp, acc.x, o.x), fmaf(sp, acc.y, o.y));
+    } else {
+      const float2 o = reinterpret_cast<const float2 *>(a.vis_in)[i];
+      r = make_float2(fmaf(-sp, acc.x, o.x), fmaf(-sp, acc.y, o.y));
+    }
+    out[i] = r;
   }
-  out[i] = r;
+}
+
+// Residual (or a plain gather) into the uv-sorted order, plus the weights.
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
+  __shared__ double2 tab[kCisTable + 1];
+  if (!kMixed && a.subtract) {
+    cis_table_init(tab);
+    __syncthreads();
+  }
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.sv.n_vis) return;
+  const int64_t i = a.sv.order[j];
+  if (!kMixed) {
+    reinterpret_cast<double *>(a.sv.wt)[j] = reinterpret_cast<const double *>(a.weight)[i];
+    double2 r = reinterpret_cast<const double2 *>(a.vis)[i];
+    if (a.subtract) {
+      const double spec = a.chan->spec[a.n_chan > 1 ? a.sv.chan[j] : 0];
+      const double2 acc = sum_f64(a.sv.u[j], a.sv.v[j], a.sv.w[j], a.src, 0, a.n_src, tab);
+      r = make_double2(fma(-spec, acc.x, r.x), fma(-spec, acc.y, r.y));
+    }
+    reinterpret_cast<double2 *>(a.sv.res)[j] = r;
+  } else {
+    reinterpret_cast<float *>(a.sv.wt)[j] = reinterpret_cast<const float *>(a.weight)[i];
+    float2 r = reinterpret_cast<const float2 *>(a.vis)[i];
+    if (a.subtract) {
+      const float spec = (float)a.chan->spec[a.n_chan > 1 ? a.sv.chan[j] : 0];
+      const float2 acc = sum_mixed(a.sv.u[j], a.sv.v[j], a.sv.w[j], a.src32, 0, a.n_src);
+      r = make_float2(fmaf(-spec, acc.x, r.x), fmaf(-spec, acc.y, r.y));
+    }
+    reinterpret_cast<float2 *>(a.sv.res)[j] = r;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_model_f64(const ModelArgs &a, hipStream_t st) {
+hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st) {
   const int64_t n = a.n_rows * a.n_chan;
   const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_model_f64, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  if (mixed)
+    hipLaunchKernelGGL(k_model<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_model<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_sorted(const ResidualArgs &a, int mixed, hipStream_t st) {
+  const int64_t blocks = (a.sv.n_vis + 255) / 256;
+  if (mixed)
+    hipLaunchKernelGGL(k_residual_sorted<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_residual_sorted<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ constexpr double kArcsec = M_PI / 648000.0;     // radians per arcsecond
 constexpr double kC = 299792458.0;              // m/s
 constexpr int kVersion = 100;                   // 0.1.0
 constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
+constexpr int kExtractChunk = 2048;             // sorted visibilities per extraction wave
 
 }  // namespace
 
@@ -44,6 +45,7 @@ struct rlf_ctx {
   struct Slot {
     std::vector<double> key;
     SrcModel *d = nullptr;
+    SrcMixed *d32 = nullptr;
     int64_t cap = 0;
     uint64_t used = 0;
   } slot[2];
@@ -62,7 +64,9 @@ struct rlf_facets {
   std::vector<double> model_key;             // shapes of the uploaded model table
   std::vector<SrcGeom> geom;
   SrcModel *d_src = nullptr;
+  SrcMixed *d_src32 = nullptr;
   SrcGeom *d_geom = nullptr;
+  Sorted sv{};                               // uv-sorted visibility layout
   DenseAcc acc{};
   Cells cells{};
   double *d_logw = nullptr;
@@ -225,36 +229,59 @@ std::vector<double> cat_key(const rlf_catalog *k) {
   return key;
 }
 
-int upload_sources(rlf_ctx *c, const rlf_catalog *k, SrcModel *dst) {
+SrcMixed to_mixed(const SrcModel &m) {
+  SrcMixed r{};
+  r.l = m.l;
+  r.m = m.m;
+  r.n1 = m.n1;
+  r.flux = (float)m.flux;
+  r.q11 = (float)m.q11;
+  r.q12x2 = (float)m.q12x2;
+  r.q22 = (float)m.q22;
+  r.theta = m.theta;
+  return r;
+}
+
+int upload_sources(rlf_ctx *c, const rlf_catalog *k, SrcModel *dst, SrcMixed *dst32) {
   std::vector<SrcModel> h((size_t)k->n_src);
-  for (int64_t s = 0; s < k->n_src; ++s) h[(size_t)s] = pack_source(c->p, k, s);
-  HIPCHK(c, hipStreamSynchronize(c->stream));      // no pending kernel may still read dst
+  std::vector<SrcMixed> h32((size_t)k->n_src);
+  for (int64_t s = 0; s < k->n_src; ++s) {
+    h[(size_t)s] = pack_source(c->p, k, s);
+    h32[(size_t)s] = to_mixed(h[(size_t)s]);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));      // no pending kernel may still read the tables
   HIPCHK(c, hipMemcpy(dst, h.data(), sizeof(SrcModel) * h.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(dst32, h32.data(), sizeof(SrcMixed) * h32.size(), hipMemcpyHostToDevice));
   return RLF_OK;
 }
 
 // Device source table for rlf_model_vis, reused while the catalogue content is unchanged.
-int model_table(rlf_ctx *c, const rlf_catalog *k, const SrcModel **out) {
+int model_table(rlf_ctx *c, const rlf_catalog *k, const SrcModel **out, const SrcMixed **out32) {
   std::vector<double> key = cat_key(k);
   ++c->tick;
   for (auto &sl : c->slot)
     if (sl.d && sl.key == key) {
       sl.used = c->tick;
       *out = sl.d;
+      *out32 = sl.d32;
       return RLF_OK;
     }
   auto &sl = c->slot[0].used <= c->slot[1].used ? c->slot[0] : c->slot[1];
   if (sl.cap < k->n_src) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     dfree(sl.d);
+    dfree(sl.d32);
     sl.cap = 0;
     if (int e = dalloc(c, &sl.d, k->n_src)) return e;
+    if (int e = dalloc(c, &sl.d32, k->n_src)) return e;
     sl.cap = k->n_src;
   }
-  if (int e = upload_sources(c, k, sl.d)) return e;
+  sl.key.clear();
+  if (int e = upload_sources(c, k, sl.d, sl.d32)) return e;
   sl.key.swap(key);
   sl.used = c->tick;
   *out = sl.d;
+  *out32 = sl.d32;
   return RLF_OK;
 }
 
@@ -281,6 +308,15 @@ int set_device(rlf_ctx *c) {
 
 void free_facets(rlf_facets *f) {
   dfree(f->d_src);
+  dfree(f->d_src32);
+  dfree(f->sv.order);
+  dfree(f->sv.u);
+  dfree(f->sv.v);
+  dfree(f->sv.w);
+  dfree(f->sv.chan);
+  if (f->sv.res) (void)hipFree(f->sv.res);
+  if (f->sv.wt) (void)hipFree(f->sv.wt);
+  f->sv.res = f->sv.wt = nullptr;
   dfree(f->d_geom);
   dfree(f->acc.count);
   dfree(f->acc.wsum);
@@ -310,6 +346,56 @@ int check_device_error(rlf_ctx *c) {
     return fail(c, RLF_ERANGE, "a visibility fell outside its facet: the observation's uvw changed after rlf_facets_create");
   }
   return RLF_OK;
+}
+
+int build_sorted(rlf_ctx *c, const rlf_obs *obs, const double mx[2], rlf_facets *f) {
+  const int64_t n = obs->n_rows * obs->n_chan;
+  if (n >= ((int64_t)1 << 32)) return fail(c, RLF_ERANGE, "more than 2^32 - 1 visibilities");
+  if (int e = chan_table(c, obs)) return e;
+  Sorted &sv = f->sv;
+  sv.n_vis = n;
+  const size_t esz = f->mixed ? 4 : 8;
+  if (int e = dalloc(c, &sv.order, n)) return e;
+  if (int e = dalloc(c, &sv.u, n)) return e;
+  if (int e = dalloc(c, &sv.v, n)) return e;
+  if (int e = dalloc(c, &sv.w, n)) return e;
+  if (int e = dalloc(c, &sv.chan, n)) return e;
+  HIPCHK(c, hipMalloc(&sv.res, 2 * esz * (size_t)n));
+  HIPCHK(c, hipMalloc(&sv.wt, esz * (size_t)n));
+  double smax = 0.0;
+  for (int k = 0; k < obs->n_chan; ++k) smax = std::fmax(smax, obs->freq_hz_host[k] / kC);
+  const double su = mx[0] * smax, svv = mx[1] * smax;
+  uint32_t *kin = nullptr, *vin = nullptr, *kout = nullptr;
+  void *tmp = nullptr;
+  int rc = RLF_OK;
+  do {
+    if ((rc = dalloc(c, &kin, n))) break;
+    if ((rc = dalloc(c, &vin, n))) break;
+    if ((rc = dalloc(c, &kout, n))) break;
+    SortKeyArgs ka{};
+    ka.u_m = obs->u_m;
+    ka.v_m = obs->v_m;
+    ka.n_rows = obs->n_rows;
+    ka.n_chan = obs->n_chan;
+    ka.chan = c->d_chan;
+    ka.inv_span_u = su > 0 ? 1.0 / (2.0 * su) : 1.0;
+    ka.inv_span_v = svv > 0 ? 1.0 / (2.0 * svv) : 1.0;
+    ka.keys = kin;
+    ka.vals = vin;
+    hipError_t e = launch_sort_keys(ka, c->stream);
+    size_t tmp_bytes = 0;
+    if (e == hipSuccess) e = sort_pairs_u32(nullptr, tmp_bytes, kin, kout, vin, sv.order, n, c->stream);
+    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1);
+    if (e == hipSuccess) e = sort_pairs_u32(tmp, tmp_bytes, kin, kout, vin, sv.order, n, c->stream);
+    if (e == hipSuccess) e = launch_sorted_static(sv, obs->u_m, obs->v_m, obs->w_m, obs->n_chan, c->d_chan, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(c, e, "uv sort of the visibilities");
+  } while (0);
+  dfree(kin);
+  dfree(vin);
+  dfree(kout);
+  if (tmp) (void)hipFree(tmp);
+  return rc;
 }
 
 }  // namespace
@@ -411,7 +497,10 @@ int rlf_destroy(rlf_ctx *c) {
   dfree(c->d_chan);
   dfree(c->d_err);
   dfree(c->d_absmax);
-  for (auto &sl : c->slot) dfree(sl.d);
+  for (auto &sl : c->slot) {
+    dfree(sl.d);
+    dfree(sl.d32);
+  }
   delete c;
   return RLF_OK;
 }
@@ -452,7 +541,8 @@ int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_
   if (int e = set_device(c)) return e;
   if (int e = chan_table(c, obs)) return e;
   const SrcModel *d_src = nullptr;
-  if (int e = model_table(c, cat, &d_src)) return e;
+  const SrcMixed *d_src32 = nullptr;
+  if (int e = model_table(c, cat, &d_src, &d_src32)) return e;
   ModelArgs a{};
   a.u_m = obs->u_m;
   a.v_m = obs->v_m;
@@ -462,11 +552,12 @@ int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_
   a.mode = mode;
   a.chan = c->d_chan;
   a.src = d_src;
+  a.src32 = d_src32;
   a.s_begin = (int32_t)src_begin;
   a.s_end = (int32_t)src_end;
   a.vis_in = obs->vis;
   a.out = out;
-  hipError_t e = c->p.precision == RLF_MIXED ? launch_model_mixed(a, c->stream) : launch_model_f64(a, c->stream);
+  hipError_t e = launch_model(a, c->p.precision == RLF_MIXED, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "model kernel launch");
   return RLF_OK;
 }
@@ -531,6 +622,7 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
   int rc = RLF_OK;
   do {
     if ((rc = dalloc(c, &f->d_src, f->n_src))) break;
+    if ((rc = dalloc(c, &f->d_src32, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_geom, f->n_src))) break;
     if ((rc = dalloc(c, &f->acc.count, total))) break;
     if ((rc = dalloc(c, &f->acc.wsum, total))) break;
@@ -573,12 +665,17 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
     delete f;
     return hip_fail(c, e, "facet buffer initialisation");
   }
-  if (int r = upload_sources(c, cat, f->d_src)) {
+  if (int r = upload_sources(c, cat, f->d_src, f->d_src32)) {
     free_facets(f);
     delete f;
     return r;
   }
   f->model_key = cat_key(cat);
+  if (int r = build_sorted(c, obs, mx, f)) {
+    free_facets(f);
+    delete f;
+    return r;
+  }
   *out = f;
   return RLF_OK;
 }
@@ -588,8 +685,9 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
   if (!c) return RLF_EINVAL;
   c->err.clear();
   if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
-  if (!residual) return fail(c, RLF_EINVAL, "residual is NULL");
   if (int e = check_obs(c, obs)) return e;
+  if (!residual && !obs->vis) return fail(c, RLF_EINVAL, "residual and obs.vis are both NULL");
+  if (obs->n_rows * obs->n_chan != f->sv.n_vis) return fail(c, RLF_EINVAL, "observation size differs from rlf_facets_create");
   if (int e = check_cat(c, cat, false)) return e;
   if (cat->n_src != f->n_src || std::memcmp(cat->alpha_arcsec, f->alpha.data(), sizeof(double) * f->n_src) != 0)
     return fail(c, RLF_EINVAL, "catalogue sources/sizes differ from rlf_facets_create");
@@ -597,24 +695,35 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
   if (int e = chan_table(c, obs)) return e;
   std::vector<double> key = cat_key(cat);
   if (key != f->model_key) {
-    if (int e = upload_sources(c, cat, f->d_src)) return e;
+    if (int e = upload_sources(c, cat, f->d_src, f->d_src32)) return e;
     f->model_key.swap(key);
   }
+  ResidualArgs ra{};
+  ra.sv = f->sv;
+  ra.n_chan = obs->n_chan;
+  ra.n_src = (int32_t)f->n_src;
+  ra.chan = c->d_chan;
+  ra.src = f->d_src;
+  ra.src32 = f->d_src32;
+  ra.vis = residual ? residual : obs->vis;
+  ra.weight = obs->weight;
+  ra.subtract = residual ? 0 : 1;
+  hipError_t e = launch_residual_sorted(ra, f->mixed, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "residual kernel launch");
   ExtractArgs a{};
-  a.u_m = obs->u_m;
-  a.v_m = obs->v_m;
-  a.w_m = obs->w_m;
-  a.n_rows = obs->n_rows;
+  a.sv = f->sv;
   a.n_chan = obs->n_chan;
   a.n_src = (int32_t)f->n_src;
+  a.n_tiles = (int32_t)((f->n_src + 63) / 64);
+  a.chunk = kExtractChunk;
+  a.n_chunks = (f->sv.n_vis + kExtractChunk - 1) / kExtractChunk;
   a.chan = c->d_chan;
   a.src = f->d_src;
+  a.src32 = f->d_src32;
   a.geom = f->d_geom;
-  a.resid = residual;
-  a.weight = obs->weight;
   a.acc = f->acc;
   a.err = c->d_err;
-  hipError_t e = f->mixed ? launch_extract_mixed(a, c->stream) : launch_extract_f64(a, c->stream);
+  e = launch_extract(a, f->mixed, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "extract kernel launch");
   CompactArgs ca{};
   ca.n_src = (int32_t)f->n_src;

@@ -22,6 +22,14 @@ struct alignas(64) SrcModel {
   double theta;              // facet field of view (radians); cell index = rint(u theta)
 };
 
+// The same constants for the mixed-precision form: phase terms stay FP64,
+// the profile runs in FP32.
+struct alignas(64) SrcMixed {
+  double l, m, n1;
+  float flux, q11, q12x2, q22;
+  double theta;
+};
+
 // Per-source facet geometry: dense accumulator block [side*side], cells
 // centred on the uv origin, index (iy+half)*side + (ix+half).
 struct SrcGeom {
@@ -59,23 +67,60 @@ struct ModelArgs {
   int32_t mode;
   const ChanTable *chan;
   const SrcModel *src;
+  const SrcMixed *src32;
   int32_t s_begin, s_end;
   const void *vis_in;        // RESIDUAL mode only
   void *out;
 };
 
-struct ExtractArgs {
-  const double *u_m, *v_m, *w_m;
+// Per-visibility arrays of a facet object in uv-sorted order (sorted once at
+// creation along a Morton curve over (u, v) in wavelengths, so every
+// source's facet cells are visited in long contiguous stretches).
+struct Sorted {
+  int64_t n_vis;
+  uint32_t *order;           // sorted position -> visibility index row*n_chan + chan
+  double *u, *v, *w;         // wavelengths
+  uint8_t *chan;             // channel of each sorted visibility
+  void *res;                 // residual, complex128 | complex64
+  void *wt;                  // weight, f64 | f32
+};
+
+struct SortKeyArgs {
+  const double *u_m, *v_m;
   int64_t n_rows;
+  int32_t n_chan;
+  const ChanTable *chan;
+  double inv_span_u, inv_span_v;   // 1 / (2 max|u|), 1 / (2 max|v|) in wavelengths
+  uint32_t *keys, *vals;
+};
+
+struct ExtractArgs {
+  Sorted sv;
+  int32_t n_chan;
+  int32_t n_src;
+  int32_t n_tiles;           // ceil(n_src / 64)
+  int32_t chunk;             // sorted visibilities per wave
+  int64_t n_chunks;
+  const ChanTable *chan;
+  const SrcModel *src;
+  const SrcMixed *src32;
+  const SrcGeom *geom;
+  DenseAcc acc;
+  uint32_t *err;             // bit 0: a cell index fell outside its facet (visibility skipped)
+};
+
+// Residual in sorted order: res[j] = vis[order[j]] - sum over sources of Eq. 1
+// (or a plain gather of a residual given in caller order).
+struct ResidualArgs {
+  Sorted sv;
   int32_t n_chan;
   int32_t n_src;
   const ChanTable *chan;
   const SrcModel *src;
-  const SrcGeom *geom;
-  const void *resid;
-  const void *weight;
-  DenseAcc acc;
-  uint32_t *err;             // bit 0: a cell index fell outside its facet (visibility skipped)
+  const SrcMixed *src32;
+  const void *vis;           // caller order
+  const void *weight;        // caller order
+  int32_t subtract;          // 1: vis - sky; 0: gather only
 };
 
 struct CompactArgs {
@@ -124,10 +169,14 @@ struct EstimateArgs {
 };
 
 // Launchers (enqueue on `st`; return the launch status).
-hipError_t launch_model_f64(const ModelArgs &a, hipStream_t st);
-hipError_t launch_model_mixed(const ModelArgs &a, hipStream_t st);
-hipError_t launch_extract_f64(const ExtractArgs &a, hipStream_t st);
-hipError_t launch_extract_mixed(const ExtractArgs &a, hipStream_t st);
+hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st);
+hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st);
+hipError_t launch_residual_sorted(const ResidualArgs &a, int mixed, hipStream_t st);
+hipError_t launch_sort_keys(const SortKeyArgs &a, hipStream_t st);
+hipError_t sort_pairs_u32(void *tmp, size_t &tmp_bytes, const uint32_t *kin, uint32_t *kout, const uint32_t *vin,
+                          uint32_t *vout, int64_t n, hipStream_t st);
+hipError_t launch_sorted_static(const Sorted &sv, const double *u_m, const double *v_m, const double *w_m,
+                                int32_t n_chan, const ChanTable *chan, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, int mixed, hipStream_t st);
 hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st);
 hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st);

@@ -182,3 +182,37 @@ def test_abi_errors_on_gpu(ctx):
         ctx.model_vis(obs, cat, torch.empty_like(obs.vis), src_begin=3, src_end=99)
     assert e.value.code == rlf.RLF_EINVAL
     f.free()
+
+
+def test_fused_residual_matches_explicit_residual(ctx):
+    """rlf_extract_facets with residual = NULL (the library subtracts the sky
+    model itself, in its sorted order) equals extraction from the residual of
+    rlf_model_vis, and the oracle; 2 channels, flagged data."""
+    import dataclasses
+    torch = G.torch_cuda()
+    cfg = dataclasses.replace(synth.small_config(0, n_ant=11, n_time=31, n_src=23), freq_hz=(1.3e9, 1.45e9))
+    o = synth.observation(0, cfg)
+    cat = synth.catalogue(cfg, np.random.default_rng(41))
+    rng = np.random.default_rng(42)
+    n = o.n_rows * o.n_chan
+    o.weight[rng.random(n) < 0.05] = 0.0
+    data = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat) + \
+        cfg.noise_sigma_jy * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    catc = G.circular(cat)
+    obs = G.make_obs(o, data)
+    resid = torch.empty_like(obs.vis)
+    ctx.model_vis(obs, catc, resid, mode=rlf.RLF_MODEL_RESIDUAL)
+    f1 = ctx.facets_create(obs, catc)
+    ctx.extract_facets(obs, catc, resid, f1)
+    a = f1.copy()
+    ctx.extract_facets(obs, catc, None, f1)
+    b = f1.copy()
+    for k in ("offsets", "ix", "iy", "count"):
+        assert np.array_equal(a[k], b[k]), k
+    resid_o = data - oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, catc)
+    scale = np.max(np.abs(resid_o))
+    for s in range(cat.n_src):
+        ref = G.oracle_facet(o, resid_o, catc, s)
+        G.check_facet(a, s, ref, scale, cat.flux_jy[s] * 1.1)
+        G.check_facet(b, s, ref, scale, cat.flux_jy[s] * 1.1)
+    f1.free()

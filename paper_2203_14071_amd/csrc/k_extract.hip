@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kXcd = 8;
 constexpr int kWaves = 4;          // waves (source tiles) per block
+constexpr int kGroup = 4;          // visibilities whose scalar loads are issued together
 
 struct Run {
   int key;                         // cell in the source's dense block, -1 = none
@@ -32,16 +33,28 @@ struct Run {
   double w, zr, zi;
 };
 
-__device__ __forceinline__ void flush(const DenseAcc &acc, int64_t base, const Run &p) {
+__device__ __forceinline__ void flush(uint32_t *__restrict__ cnt, double *__restrict__ ws, double *__restrict__ zre,
+                                      double *__restrict__ zim, int64_t base, const Run &p) {
   const int64_t k = base + p.key;
-  atomicAdd(acc.count + k, p.n);
-  unsafeAtomicAdd(acc.wsum + k, p.w);
-  unsafeAtomicAdd(acc.zre + k, p.zr);
-  unsafeAtomicAdd(acc.zim + k, p.zi);
+  atomicAdd(cnt + k, p.n);
+  unsafeAtomicAdd(ws + k, p.w);
+  unsafeAtomicAdd(zre + k, p.zr);
+  unsafeAtomicAdd(zim + k, p.zi);
 }
 
+// The read-only visibility data and the atomic targets are separate
+// restrict-qualified kernel parameters: with no possible aliasing the
+// compiler keeps the per-visibility loads scalar (s_load) although the loop
+// issues atomics.  Visibilities are taken in groups of kGroup whose loads are
+// issued together; the sorted arrays are padded so a group never reads past
+// the end, and padding carries weight 0.
 template <bool kMixed>
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double *__restrict__ su,
+                                                 const double *__restrict__ sv, const double *__restrict__ sw,
+                                                 const uint32_t *__restrict__ sch4, const void *__restrict__ sres,
+                                                 const void *__restrict__ swt, const double *__restrict__ spec_tab,
+                                                 uint32_t *__restrict__ cnt, double *__restrict__ ws,
+                                                 double *__restrict__ zre, double *__restrict__ zim) {
   __shared__ double2 tab[kCisTable + 1];
   if (!kMixed) {
     cis_table_init(tab);
@@ -59,22 +72,35 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   const bool active = s_raw < a.n_src;
   const int s = active ? s_raw : a.n_src - 1;
   const SrcGeom g = a.geom[s];
-  const double theta = a.src[s].theta;
   const int64_t j0 = chunk * (int64_t)a.chunk;
   const int64_t j1 = min(a.sv.n_vis, j0 + (int64_t)a.chunk);
-  const double spec0 = a.chan->spec[0];
+  const bool multi = a.n_chan > 1;
 
   Run cur{-1, 0u, 0.0, 0.0, 0.0};
   if (!kMixed) {
     const SrcModel p = a.src[s];
-    const double2 *__restrict__ res = reinterpret_cast<const double2 *>(a.sv.res);
-    const double *__restrict__ wt = reinterpret_cast<const double *>(a.sv.wt);
-    for (int64_t j = j0; j < j1; ++j) {
-      const double ww = wt[j];
+    const double2 *__restrict__ res = reinterpret_cast<const double2 *>(sres);
+    const double *__restrict__ wt = reinterpret_cast<const double *>(swt);
+    for (int64_t jg = j0; jg < j1; jg += kGroup) {
+      double wwg[kGroup], ug[kGroup], vg[kGroup], wg[kGroup], spg[kGroup];
+      double2 rg[kGroup];
+      const uint32_t chg = multi ? sch4[jg / 4] : 0u;
+#pragma unroll
+      for (int t = 0; t < kGroup; ++t) {
+        wwg[t] = wt[jg + t];
+        ug[t] = su[jg + t];
+        vg[t] = sv[jg + t];
+        wg[t] = sw[jg + t];
+        rg[t] = res[jg + t];
+        spg[t] = spec_tab[(chg >> (8 * t)) & 0xffu];
+      }
+#pragma unroll
+      for (int t = 0; t < kGroup; ++t) {
+      const double ww = wwg[t];
       if (!(ww > 0.0)) continue;                                   // uniform
-      const double u = a.sv.u[j], v = a.sv.v[j], w = a.sv.w[j];
-      const double2 r = res[j];
-      const double spec = a.n_chan > 1 ? a.chan->spec[a.sv.chan[j]] : spec0;
+      const double u = ug[t], v = vg[t], w = wg[t];
+      const double2 r = rg[t];
+      const double spec = spg[t];
       const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
       const double2 cs = cis2pi_f64(ph, tab);
       double zr = fma(r.x, cs.x, r.y * cs.y);                      // residual * exp(-2 pi i ph)
@@ -82,13 +108,13 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
       const double x = fma(p.q11, u * u, fma(p.q12x2, u * v, fma(p.q22, v * v, 1.0)));
       const double q = rsqrt_f64(x);
       zr = fma(spec * p.flux, q * q * q, zr);                      // own model, real after the shift
-      const int ix = (int)rint(__dmul_rn(u, theta));
-      const int iy = (int)rint(__dmul_rn(v, theta));
+      const int ix = (int)rint(__dmul_rn(u, p.theta));
+      const int iy = (int)rint(__dmul_rn(v, p.theta));
       const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
       const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
       const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
       if (key != cur.key) {
-        if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
+        if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
         if (!inb && active) atomicOr(a.err, 1u);
         cur.key = key;
         cur.n = 0u;
@@ -98,17 +124,33 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
       cur.w += ww;
       cur.zr = fma(ww, zr, cur.zr);
       cur.zi = fma(ww, zi, cur.zi);
+      }
     }
   } else {
     const SrcMixed p = a.src32[s];
-    const float2 *__restrict__ res = reinterpret_cast<const float2 *>(a.sv.res);
-    const float *__restrict__ wt = reinterpret_cast<const float *>(a.sv.wt);
-    for (int64_t j = j0; j < j1; ++j) {
-      const float ww = wt[j];
+    const float2 *__restrict__ res = reinterpret_cast<const float2 *>(sres);
+    const float *__restrict__ wt = reinterpret_cast<const float *>(swt);
+    for (int64_t jg = j0; jg < j1; jg += kGroup) {
+      float wwg[kGroup];
+      double ug[kGroup], vg[kGroup], wg[kGroup], spg[kGroup];
+      float2 rg[kGroup];
+      const uint32_t chg = multi ? sch4[jg / 4] : 0u;
+#pragma unroll
+      for (int t = 0; t < kGroup; ++t) {
+        wwg[t] = wt[jg + t];
+        ug[t] = su[jg + t];
+        vg[t] = sv[jg + t];
+        wg[t] = sw[jg + t];
+        rg[t] = res[jg + t];
+        spg[t] = spec_tab[(chg >> (8 * t)) & 0xffu];
+      }
+#pragma unroll
+      for (int tt = 0; tt < kGroup; ++tt) {
+      const float ww = wwg[tt];
       if (!(ww > 0.0f)) continue;                                  // uniform
-      const double u = a.sv.u[j], v = a.sv.v[j], w = a.sv.w[j];
-      const float2 r = res[j];
-      const float spec = (float)(a.n_chan > 1 ? a.chan->spec[a.sv.chan[j]] : spec0);
+      const double u = ug[tt], v = vg[tt], w = wg[tt];
+      const float2 r = rg[tt];
+      const float spec = (float)spg[tt];
       const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
       const float t = (float)(ph - rint(ph));                      // turns, |t| <= 1/2
       const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
@@ -118,13 +160,13 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
       const float x = fmaf(p.q11, uf * uf, fmaf(p.q12x2, uf * vf, fmaf(p.q22, vf * vf, 1.0f)));
       const float q = __builtin_amdgcn_rsqf(x);
       zr = fmaf(spec * p.flux, q * q * q, zr);
-      const int ix = (int)rint(__dmul_rn(u, theta));
-      const int iy = (int)rint(__dmul_rn(v, theta));
+      const int ix = (int)rint(__dmul_rn(u, p.theta));
+      const int iy = (int)rint(__dmul_rn(v, p.theta));
       const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
       const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
       const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
       if (key != cur.key) {
-        if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
+        if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
         if (!inb && active) atomicOr(a.err, 1u);
         cur.key = key;
         cur.n = 0u;
@@ -135,9 +177,10 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
       cur.w += wd;
       cur.zr = fma(wd, (double)zr, cur.zr);
       cur.zi = fma(wd, (double)zi, cur.zi);
+      }
     }
   }
-  if (cur.key >= 0 && active) flush(a.acc, g.base, cur);
+  if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
 }
 
 }  // namespace
@@ -145,10 +188,13 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
 hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st) {
   const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
   const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
+  const Sorted &v = a.sv;
   if (mixed)
-    hipLaunchKernelGGL(k_extract<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a);
+    hipLaunchKernelGGL(k_extract<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.u, v.v, v.w,
+                       reinterpret_cast<const uint32_t *>(v.chan), v.res, v.wt, a.chan->spec, a.acc.count, a.acc.wsum, a.acc.zre, a.acc.zim);
   else
-    hipLaunchKernelGGL(k_extract<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a);
+    hipLaunchKernelGGL(k_extract<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.u, v.v, v.w,
+                       reinterpret_cast<const uint32_t *>(v.chan), v.res, v.wt, a.chan->spec, a.acc.count, a.acc.wsum, a.acc.zre, a.acc.zim);
   return hipGetLastError();
 }
 

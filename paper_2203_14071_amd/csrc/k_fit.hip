@@ -81,13 +81,12 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r_arg) {
 #pragma unroll
     for (int k = 0; k < R; ++k) sk[k] = k < num_r ? (float)(a.sk[k] * g) : 0.0f;
     const float4 *__restrict__ cells = a.fit32;
-    for (int64_t cb = c0; cb < c1; cb += kBlock) {
-      const int64_t ce = min(c1, cb + (int64_t)kBlock);
+    auto block = [&](int64_t cb, int n) {
       float d[R], m[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) d[k] = m[k] = 0.0f;
-      for (int64_t c = cb; c < ce; ++c) {
-        const float4 cl = cells[c];
+      for (int t = 0; t < n; ++t) {
+        const float4 cl = cells[cb + t];
         const float ku = fmaf(a11, cl.x, a12 * cl.y);
         const float kv = fmaf(a12, cl.x, a22 * cl.y);
         const float q = fmaf(ku, ku, kv * kv);
@@ -106,7 +105,11 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r_arg) {
         D[k] += (double)d[k];
         M[k] += (double)m[k];
       }
-    }
+    };
+    int64_t cb = c0;
+#pragma clang loop unroll(disable)
+    for (; cb + kBlock <= c1; cb += kBlock) block(cb, kBlock);
+    if (cb < c1) block(cb, (int)(c1 - cb));
   }
   if (c1 == c0) {
     *out = NAN;

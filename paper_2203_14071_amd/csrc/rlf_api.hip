@@ -23,6 +23,7 @@ constexpr double kC = 299792458.0;              // m/s
 constexpr int kVersion = 100;                   // 0.1.0
 constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
 constexpr int kExtractChunk = 2048;             // sorted visibilities per extraction wave
+constexpr int kSortedPad = 64;                  // zero-weight tail of the sorted arrays
 
 }  // namespace
 
@@ -355,13 +356,22 @@ int build_sorted(rlf_ctx *c, const rlf_obs *obs, const double mx[2], rlf_facets 
   Sorted &sv = f->sv;
   sv.n_vis = n;
   const size_t esz = f->mixed ? 4 : 8;
+  // the extraction reads visibilities in groups: pad every array read there,
+  // with zero weight (skipped) and zero coordinates in the padding
+  const int64_t np = n + kSortedPad;
   if (int e = dalloc(c, &sv.order, n)) return e;
-  if (int e = dalloc(c, &sv.u, n)) return e;
-  if (int e = dalloc(c, &sv.v, n)) return e;
-  if (int e = dalloc(c, &sv.w, n)) return e;
-  if (int e = dalloc(c, &sv.chan, n)) return e;
-  HIPCHK(c, hipMalloc(&sv.res, 2 * esz * (size_t)n));
-  HIPCHK(c, hipMalloc(&sv.wt, esz * (size_t)n));
+  if (int e = dalloc(c, &sv.u, np)) return e;
+  if (int e = dalloc(c, &sv.v, np)) return e;
+  if (int e = dalloc(c, &sv.w, np)) return e;
+  if (int e = dalloc(c, &sv.chan, np)) return e;
+  HIPCHK(c, hipMalloc(&sv.res, 2 * esz * (size_t)np));
+  HIPCHK(c, hipMalloc(&sv.wt, esz * (size_t)np));
+  HIPCHK(c, hipMemset(sv.u, 0, sizeof(double) * (size_t)np));
+  HIPCHK(c, hipMemset(sv.v, 0, sizeof(double) * (size_t)np));
+  HIPCHK(c, hipMemset(sv.w, 0, sizeof(double) * (size_t)np));
+  HIPCHK(c, hipMemset(sv.chan, 0, (size_t)np));
+  HIPCHK(c, hipMemset(sv.res, 0, 2 * esz * (size_t)np));
+  HIPCHK(c, hipMemset(sv.wt, 0, esz * (size_t)np));
   double smax = 0.0;
   for (int k = 0; k < obs->n_chan; ++k) smax = std::fmax(smax, obs->freq_hz_host[k] / kC);
   const double su = mx[0] * smax, svv = mx[1] * smax;

@@ -12,7 +12,8 @@ star-forming galaxies), whose Measurement Set, antenna layout and catalogue
 are not available.  Shapes and sizes follow that observation; the value
 distributions are the ones stated in each config below.
 
-Random streams use numpy's PCG64 with seed = 1000*config + stream:
+Random streams use numpy's PCG64 with seed = 1000*config + stream (config 2,
+the precision form of config 1, uses config 1's seeds):
   +1 antennas, +2 catalogue (positions, flux, scale, ellipticity in that
   order), +3 noise (real parts then imaginary parts), +4 training set,
   +5 network initialisation.
@@ -92,8 +93,13 @@ POP_SIZE_ADD, POP_SIZE_ESP, POP_SIZE_SCATTER = -0.93, 0.33, 0.3136
 SIZE_MIN_ARCSEC, SIZE_MAX_ARCSEC = 0.3, 3.5
 
 
+# Config 2 is config 1 in the mixed-precision form: it draws config 1's streams.
+SEED_CONFIG = {2: 1}
+
+
 def rng(cfg_index: int, stream: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(1000 * cfg_index + stream))
+    base = SEED_CONFIG.get(cfg_index, cfg_index)
+    return np.random.Generator(np.random.PCG64(1000 * base + stream))
 
 
 def antennas(cfg: Config, g: np.random.Generator) -> np.ndarray:

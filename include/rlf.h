@@ -43,6 +43,7 @@ extern "C" {
 
 typedef struct rlf_ctx rlf_ctx;        /* opaque: device, stream, parameters, tables */
 typedef struct rlf_facets rlf_facets;  /* opaque: facet geometry + device buffers for one catalogue */
+typedef struct rlf_pass rlf_pass;      /* opaque: a captured, replayable pass over all sources */
 
 typedef enum {
   RLF_OK = 0,
@@ -241,6 +242,35 @@ typedef struct {
  * and the flags. */
 int rlf_fit_sources(rlf_ctx *ctx, const rlf_facets *facets, const rlf_fit_opts *opts,
                     rlf_fit_out *out);
+
+/* Batched pass over every source (Sec. 2.2-2.4 in one unit): the residual of
+ * this catalogue's sky model (as rlf_extract_facets with residual = NULL),
+ * extraction, compaction, the likelihood grid and the estimate, captured
+ * once into a HIP graph and replayed by rlf_pass_launch on the context's
+ * stream.  The likelihood runs as one persistent work-queue launch: sources
+ * in decreasing order of facet cell count, each work item covering tile*64
+ * grid points of one source.  The tile for each facet-size bucket (cells
+ * < 256, < 1024, < 4096, >= 4096) is autotuned at creation by timing the
+ * candidates 1, 2, 4, 8 on the pass's own facets, unless `tune_path` (a text
+ * file, may be NULL) already holds a choice for this precision and knot
+ * count; new choices are written back to it.  Creation runs the pass once
+ * eagerly and synchronises.  Replays read and write the same buffers given
+ * here (obs->vis may be refilled between replays); the catalogue, the
+ * observation geometry and weights must stay as they were.  opts as for
+ * rlf_fit_sources (the windowed mode uses its own windowed launch). */
+int rlf_pass_create(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets *facets,
+                    const rlf_fit_opts *opts, const rlf_fit_out *out, const char *tune_path,
+                    rlf_pass **pass);
+
+/* Enqueue one replay of the pass on the context's stream. */
+int rlf_pass_launch(rlf_pass *pass);
+
+/* The chosen tile per bucket, and how it was chosen (0 bucket empty,
+ * 1 timed now, 2 read from the table).  Either pointer may be NULL. */
+int rlf_pass_tiles(const rlf_pass *pass, int32_t *tiles /*[4]*/, int32_t *tuned /*[4]*/);
+
+/* Free a pass (NULL is a no-op); synchronises. */
+int rlf_pass_free(rlf_pass *pass);
 
 #ifdef __cplusplus
 }

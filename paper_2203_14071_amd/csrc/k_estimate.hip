@@ -52,8 +52,11 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
       const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
       if (!grid_valid(i1, i2, a.n_e, a.half_r2)) S[f] = -INFINITY;
     }
-    for (int j = threadIdx.x; j < a.n_valid; j += kThreads)
-      S[a.epts[j]] = n_cells > 0 ? L[j] : -INFINITY;
+    for (int j = threadIdx.x; j < a.n_valid; j += kThreads) {
+      const int f = a.epts[j];
+      const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+      S[f] = (n_cells > 0 && in_box(a.window, s, i1, i2)) ? L[j] : -INFINITY;
+    }
   }
 
   // pass 1: maximum, smallest index on ties (each thread scans increasing j)
@@ -62,6 +65,11 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
   if (n_cells > 0) {
     for (int j = threadIdx.x; j < a.n_valid; j += kThreads) {
       const double v = L[j];
+      if (a.window) {
+        const int f = a.epts[j];
+        const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+        if (!in_box(a.window, s, i1, i2)) continue;
+      }
       if (v > best) {
         best = v;
         bi = j;
@@ -117,6 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
     if (v >= thr) {
       const int f = a.epts[j];
       const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+      if (!in_box(a.window, s, i1, i2)) continue;
       const double w = exp(v - best);
       const double x1 = (double)(i1 - ctr) * a.e_step, x2 = (double)(i2 - ctr) * a.e_step;
       sw += w;
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
     if (v >= thr) {
       const int f = a.epts[j];
       const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+      if (!in_box(a.window, s, i1, i2)) continue;
       const double w = exp(v - best);
       const double d1 = (double)(i1 - ctr) * a.e_step - m1, d2 = (double)(i2 - ctr) * a.e_step - m2;
       c11 += w * d1 * d1;

@@ -24,27 +24,14 @@ namespace {
 
 constexpr int kBlock = 32;
 
-__device__ __forceinline__ bool in_window(const int32_t *win, int s, int i1, int i2) {
-  if (!win) return true;
-  const int4 b = reinterpret_cast<const int4 *>(win)[s];
-  return i1 >= b.x && i1 <= b.y && i2 >= b.z && i2 <= b.w;
-}
-
+// ln L(e) at valid grid point j (index into the valid-point list) of source s.
 template <int R, bool kExact, bool kMixed>
-__global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r_arg) {
+__device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int s, int j) {
   const int num_r = kExact ? R : num_r_arg;
-  const int s = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.n_valid) return;
   double *out = a.lsurf + (int64_t)s * a.n_valid + j;
-  if (a.redo && !a.redo[s]) return;
   const int idx = a.epts[j];
   const int i1 = idx / a.n_e, i2 = idx - (idx / a.n_e) * a.n_e;
   const int ctr = (a.n_e - 1) / 2;
-  if (!in_window(a.window, s, i1, i2)) {
-    *out = -INFINITY;
-    return;
-  }
   const double e1 = (double)(i1 - ctr) * a.e_step;
   const double e2 = (double)(i2 - ctr) * a.e_step;
   const double det = 1.0 - e1 * e1 - e2 * e2;
@@ -132,23 +119,119 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r_arg) {
   *out = mx + log(acc);
 }
 
+
+// Grid launch: blockIdx.y = source, one thread per valid grid point.
+template <int R, bool kExact, bool kMixed>
+__global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
+  const int s = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_valid) return;
+  if (a.redo && !a.redo[s]) return;
+  eval_point<R, kExact, kMixed>(a, num_r, s, j);
+}
+
+// Windowed launch: blockIdx.y = source; threads enumerate the source's
+// inclusive box (i1lo, i1hi, i2lo, i2hi) row-major and evaluate its valid
+// points.  Points outside the box are not evaluated (the estimator skips them).
+template <int R, bool kExact, bool kMixed>
+__global__ __launch_bounds__(256) void k_fit_window(FitArgs a, int num_r) {
+  const int s = blockIdx.y;
+  const int4 b = reinterpret_cast<const int4 *>(a.window)[s];
+  const int w2 = b.w - b.z + 1;
+  const int area = (b.y - b.x + 1) * w2;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < area; t += gridDim.x * blockDim.x) {
+    const int i1 = b.x + t / w2, i2 = b.z + t % w2;
+    if (i1 < 0 || i2 < 0 || i1 >= a.n_e || i2 >= a.n_e) continue;
+    const int j = a.valid_index[i1 * a.n_e + i2];
+    if (j >= 0) eval_point<R, kExact, kMixed>(a, num_r, s, j);
+  }
+}
+
+// Persistent work queue: a grid sized to the resident capacity; each wave
+// claims items with one atomic; item -> (rank, piece) by binary search of the
+// per-rank item offsets; a rank is a source (ranks ordered by decreasing cell
+// count, so the longest items go first), a piece is tile*64 consecutive valid
+// grid points.  Every wave leaves when the counter passes the item count.
+template <int R, bool kExact, bool kMixed>
+__global__ __launch_bounds__(256) void k_fit_queue(FitArgs a, QueueArgs q, int num_r) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(q.counter, 1u);
+    item = __shfl(item, 0);
+    if ((int64_t)item >= q.n_items) break;
+    int lo = 0, hi = q.n_rank;                          // item_start[lo] <= item < item_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (q.item_start[mid] <= (int64_t)item) lo = mid;
+      else hi = mid;
+    }
+    const int s = q.order[lo];
+    const int tile = q.tile[lo];
+    const int64_t piece = (int64_t)item - q.item_start[lo];
+    for (int t = 0; t < tile; ++t) {
+      const int64_t j = (piece * tile + t) * 64 + lane;
+      if (j < a.n_valid) eval_point<R, kExact, kMixed>(a, num_r, s, (int)j);
+    }
+  }
+}
+
+__global__ void k_reset_counter(uint32_t *c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
+#define RLF_FIT_DISPATCH(KERNEL, GRID, ...)                                                         \
+  do {                                                                                              \
+    if (a.num_r == 20)                                                                              \
+      hipLaunchKernelGGL((KERNEL<20, true, kMixed>), GRID, dim3(256), 0, st, __VA_ARGS__, 20);     \
+    else if (a.num_r == 23)                                                                         \
+      hipLaunchKernelGGL((KERNEL<23, true, kMixed>), GRID, dim3(256), 0, st, __VA_ARGS__, 23);     \
+    else if (a.num_r <= 8)                                                                          \
+      hipLaunchKernelGGL((KERNEL<8, false, kMixed>), GRID, dim3(256), 0, st, __VA_ARGS__, a.num_r); \
+    else                                                                                            \
+      hipLaunchKernelGGL((KERNEL<kMaxKnots, false, kMixed>), GRID, dim3(256), 0, st, __VA_ARGS__,  \
+                         a.num_r);                                                                  \
+  } while (0)
+
 template <bool kMixed>
 hipError_t launch(const FitArgs &a, hipStream_t st) {
-  const dim3 grid((a.n_valid + 255) / 256, a.n_src);
-  if (a.num_r == 20)
-    hipLaunchKernelGGL((k_fit<20, true, kMixed>), grid, dim3(256), 0, st, a, 20);
-  else if (a.num_r == 23)
-    hipLaunchKernelGGL((k_fit<23, true, kMixed>), grid, dim3(256), 0, st, a, 23);
-  else if (a.num_r <= 8)
-    hipLaunchKernelGGL((k_fit<8, false, kMixed>), grid, dim3(256), 0, st, a, a.num_r);
-  else
-    hipLaunchKernelGGL((k_fit<kMaxKnots, false, kMixed>), grid, dim3(256), 0, st, a, a.num_r);
+  if (a.window) {
+    RLF_FIT_DISPATCH(k_fit_window, dim3(a.window_blocks, a.n_src), a);
+  } else {
+    RLF_FIT_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
+  }
   return hipGetLastError();
+}
+
+template <bool kMixed>
+hipError_t launch_q(const FitArgs &a, const QueueArgs &q, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, q.counter);
+  RLF_FIT_DISPATCH(k_fit_queue, dim3(blocks), a, q);
+  return hipGetLastError();
+}
+
+template <bool kMixed>
+int queue_blocks_per_cu(int num_r) {
+  int n = 0;
+  hipError_t e;
+  if (num_r == 20) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit_queue<20, true, kMixed>, 256, 0);
+  else if (num_r == 23) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit_queue<23, true, kMixed>, 256, 0);
+  else if (num_r <= 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit_queue<8, false, kMixed>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fit_queue<kMaxKnots, false, kMixed>, 256, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace
 
 hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st) { return launch<false>(a, st); }
 hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st) { return launch<true>(a, st); }
+
+hipError_t launch_fit_queue(const FitArgs &a, const QueueArgs &q, int mixed, int blocks, hipStream_t st) {
+  return mixed ? launch_q<true>(a, q, blocks, st) : launch_q<false>(a, q, blocks, st);
+}
+
+int fit_queue_blocks_per_cu(int mixed, int num_r) {
+  return mixed ? queue_blocks_per_cu<true>(num_r) : queue_blocks_per_cu<false>(num_r);
+}
 
 }  // namespace rlf

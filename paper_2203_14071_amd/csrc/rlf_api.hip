@@ -11,8 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "rlf.h"
-#include "rlf_internal.h"
+#include "rlf_objects.h"
 
 using namespace rlf;
 
@@ -27,55 +26,7 @@ constexpr int kSortedPad = 64;                  // zero-weight tail of the sorte
 
 }  // namespace
 
-struct rlf_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  rlf_params p{};
-  std::string err;
-  // ellipticity grid
-  int n_valid = 0;
-  int half_r2 = 0;
-  int32_t *d_epts = nullptr;
-  // scale-length knots
-  std::vector<double> knots, ck;
-  double *d_sk = nullptr;
-  // channel table (cached by content)
-  std::vector<double> chan_key;
-  ChanTable *d_chan = nullptr;
-  // source tables of rlf_model_vis (two slots, reused by content)
-  struct Slot {
-    std::vector<double> key;
-    SrcModel *d = nullptr;
-    SrcMixed *d32 = nullptr;
-    int64_t cap = 0;
-    uint64_t used = 0;
-  } slot[2];
-  uint64_t tick = 0;
-  uint32_t *d_err = nullptr;
-  double *d_absmax = nullptr;
-};
-
-struct rlf_facets {
-  rlf_ctx *ctx = nullptr;
-  int64_t n_src = 0;
-  int64_t dense_total = 0;
-  int mixed = 0;
-  std::vector<double> alpha;                 // catalogue sizes at creation
-  std::vector<double> theta;
-  std::vector<double> model_key;             // shapes of the uploaded model table
-  std::vector<SrcGeom> geom;
-  SrcModel *d_src = nullptr;
-  SrcMixed *d_src32 = nullptr;
-  SrcGeom *d_geom = nullptr;
-  Sorted sv{};                               // uv-sorted visibility layout
-  DenseAcc acc{};
-  Cells cells{};
-  double *d_logw = nullptr;
-  double *d_lsurf = nullptr;
-  int32_t *d_redo = nullptr;
-};
-
-namespace {
+namespace rlf {
 
 int fail(rlf_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -86,30 +37,9 @@ int hip_fail(rlf_ctx *c, hipError_t e, const char *what) {
   return fail(c, RLF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(ctx, call)                              \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
-  } while (0)
+}  // namespace rlf
 
-template <class T>
-int dalloc(rlf_ctx *c, T **p, int64_t n) {
-  *p = nullptr;
-  if (n <= 0) n = 1;
-  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(c, RLF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  }
-  return RLF_OK;
-}
-
-template <class T>
-void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
-  p = nullptr;
-}
+namespace {
 
 bool is_fin(double x) { return std::isfinite(x); }
 
@@ -462,8 +392,12 @@ int rlf_create(rlf_ctx **out, int device, void *hip_stream, const rlf_params *p)
       for (int i2 = 0; i2 < p->n_e; ++i2)
         if ((i1 - ctr) * (i1 - ctr) + (i2 - ctr) * (i2 - ctr) < c->half_r2) ep.push_back(i1 * p->n_e + i2);
     c->n_valid = (int)ep.size();
+    std::vector<int32_t> vidx((size_t)p->n_e * p->n_e, -1);
+    for (size_t j = 0; j < ep.size(); ++j) vidx[(size_t)ep[j]] = (int32_t)j;
     if ((rc = dalloc(c, &c->d_epts, c->n_valid))) break;
-    if (hipMemcpy(c->d_epts, ep.data(), sizeof(int32_t) * ep.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if ((rc = dalloc(c, &c->d_vidx, (int64_t)vidx.size()))) break;
+    if (hipMemcpy(c->d_epts, ep.data(), sizeof(int32_t) * ep.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_vidx, vidx.data(), sizeof(int32_t) * vidx.size(), hipMemcpyHostToDevice) != hipSuccess) {
       rc = RLF_EDEVICE;
       break;
     }
@@ -503,6 +437,7 @@ int rlf_destroy(rlf_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   dfree(c->d_epts);
+  dfree(c->d_vidx);
   dfree(c->d_sk);
   dfree(c->d_chan);
   dfree(c->d_err);
@@ -811,6 +746,15 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   if (o.mode == 1 && !o.window) return fail(c, RLF_EINVAL, "windowed mode needs opts.window");
   if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
   if (int e = set_device(c)) return e;
+  return enqueue_fit(c, f, o, *out, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace rlf {
+
+int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
+                const QueueArgs *queue, int queue_blocks) {
   const bool windowed = o.mode == 1;
   FitArgs fa{};
   fa.n_src = (int32_t)f->n_src;
@@ -819,12 +763,14 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   fa.num_r = c->p.num_r;
   fa.e_step = c->p.e_step;
   fa.epts = c->d_epts;
+  fa.valid_index = c->d_vidx;
   fa.sk = c->d_sk;
   fa.logw = f->d_logw;
   fa.offsets = f->cells.offsets;
   fa.fit64 = f->cells.fit64;
   fa.fit32 = f->cells.fit32;
   fa.window = windowed ? o.window : nullptr;
+  fa.window_blocks = 4;
   fa.redo = nullptr;
   fa.lsurf = f->d_lsurf;
   EstimateArgs ea{};
@@ -842,17 +788,21 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   ea.window = fa.window;
   ea.redo = nullptr;
   ea.redo_out = (windowed && o.fallback) ? f->d_redo : nullptr;
-  ea.e1 = out->e1;
-  ea.e2 = out->e2;
-  ea.s1 = out->s1;
-  ea.s2 = out->s2;
-  ea.c12 = out->c12;
-  ea.lmax = out->lmax;
-  ea.argmax = out->argmax;
-  ea.n_above = out->n_above;
-  ea.flags = out->flags;
-  ea.surface = o.want_surface ? out->surface : nullptr;
-  hipError_t e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);
+  ea.e1 = out.e1;
+  ea.e2 = out.e2;
+  ea.s1 = out.s1;
+  ea.s2 = out.s2;
+  ea.c12 = out.c12;
+  ea.lmax = out.lmax;
+  ea.argmax = out.argmax;
+  ea.n_above = out.n_above;
+  ea.flags = out.flags;
+  ea.surface = o.want_surface ? out.surface : nullptr;
+  hipError_t e;
+  if (queue && !windowed)
+    e = launch_fit_queue(fa, *queue, f->mixed, queue_blocks, c->stream);
+  else
+    e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "fit kernel launch");
   e = launch_estimate(ea, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "estimate kernel launch");
@@ -870,4 +820,5 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   return RLF_OK;
 }
 
-}  // extern "C"
+}  // namespace rlf
+

@@ -143,9 +143,21 @@ struct FitArgs {
   const int64_t *offsets;
   const double4 *fit64;
   const float4 *fit32;
-  const int32_t *window;     // [n_src*4] or null
+  const int32_t *window;     // [n_src*4] inclusive grid boxes, or null (full grid)
+  int32_t window_blocks;     // windowed launch: blocks per source
+  const int32_t *valid_index; // [n_e*n_e] flat grid index -> valid-point index, -1 if |e| >= 1
   const int32_t *redo;       // fallback pass: [n_src] nonzero = evaluate; null = all
-  double *lsurf;             // [n_src*n_valid] ln L(e); -inf where not evaluated
+  double *lsurf;             // [n_src*n_valid] ln L(e) of the evaluated points
+};
+
+// Work queue of the persistent likelihood kernel.
+struct QueueArgs {
+  const int32_t *order;      // [n_rank] source of each rank (decreasing cell count)
+  const int64_t *item_start; // [n_rank+1] first item of each rank
+  const int32_t *tile;       // [n_rank] items cover tile*64 valid grid points
+  int32_t n_rank;
+  int64_t n_items;
+  uint32_t *counter;
 };
 
 struct EstimateArgs {
@@ -180,6 +192,8 @@ hipError_t launch_sorted_static(const Sorted &sv, const double *u_m, const doubl
 hipError_t launch_compact(const CompactArgs &a, int mixed, hipStream_t st);
 hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st);
 hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st);
+hipError_t launch_fit_queue(const FitArgs &a, const QueueArgs &q, int mixed, int blocks, hipStream_t st);
+int fit_queue_blocks_per_cu(int mixed, int num_r);
 hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);

@@ -1,0 +1,100 @@
+// Library-private definitions shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "rlf.h"
+#include "rlf_internal.h"
+
+using namespace rlf;
+
+struct rlf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rlf_params p{};
+  std::string err;
+  // ellipticity grid
+  int n_valid = 0;
+  int half_r2 = 0;
+  int32_t *d_epts = nullptr;
+  int32_t *d_vidx = nullptr;                 // flat grid index -> valid-point index or -1
+  // scale-length knots
+  std::vector<double> knots, ck;
+  double *d_sk = nullptr;
+  // channel table (cached by content)
+  std::vector<double> chan_key;
+  ChanTable *d_chan = nullptr;
+  // source tables of rlf_model_vis (two slots, reused by content)
+  struct Slot {
+    std::vector<double> key;
+    SrcModel *d = nullptr;
+    SrcMixed *d32 = nullptr;
+    int64_t cap = 0;
+    uint64_t used = 0;
+  } slot[2];
+  uint64_t tick = 0;
+  uint32_t *d_err = nullptr;
+  double *d_absmax = nullptr;
+};
+
+struct rlf_facets {
+  rlf_ctx *ctx = nullptr;
+  int64_t n_src = 0;
+  int64_t dense_total = 0;
+  int mixed = 0;
+  std::vector<double> alpha;                 // catalogue sizes at creation
+  std::vector<double> theta;
+  std::vector<double> model_key;             // shapes of the uploaded model table
+  std::vector<SrcGeom> geom;
+  SrcModel *d_src = nullptr;
+  SrcMixed *d_src32 = nullptr;
+  SrcGeom *d_geom = nullptr;
+  Sorted sv{};                               // uv-sorted visibility layout
+  DenseAcc acc{};
+  Cells cells{};
+  double *d_logw = nullptr;
+  double *d_lsurf = nullptr;
+  int32_t *d_redo = nullptr;
+};
+
+
+namespace rlf {
+
+int fail(rlf_ctx *c, int code, const std::string &msg);
+int hip_fail(rlf_ctx *c, hipError_t e, const char *what);
+
+#define HIPCHK(ctx, call)                                    \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return rlf::hip_fail(ctx, e_, #call); \
+  } while (0)
+
+template <class T>
+int dalloc(rlf_ctx *c, T **p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, RLF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return RLF_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// Enqueue the likelihood grid and the estimator for every source of the
+// last extraction (rlf_fit_sources without argument checks); `queue` selects
+// the persistent work-queue kernel instead of the grid launch.
+int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
+                const QueueArgs *queue, int queue_blocks);
+
+}  // namespace rlf

@@ -76,6 +76,12 @@ _SIGNATURES = {
     "rlf_facets_copy": ([_c_vp, _c_vp, _c_lp, _c_ip, _c_ip, _c_ip, _c_dp, _c_dp, _c_dp], ctypes.c_int),
     "rlf_facets_free": ([_c_vp], ctypes.c_int),
     "rlf_fit_sources": ([_c_vp, _c_vp, ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out)], ctypes.c_int),
+    "rlf_pass_create": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), _c_vp,
+                         ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out), ctypes.c_char_p,
+                         ctypes.POINTER(_c_vp)], ctypes.c_int),
+    "rlf_pass_launch": ([_c_vp], ctypes.c_int),
+    "rlf_pass_tiles": ([_c_vp, _c_ip, _c_ip], ctypes.c_int),
+    "rlf_pass_free": ([_c_vp], ctypes.c_int),
 }
 
 _lib = None
@@ -214,16 +220,58 @@ class Context:
     def fit_sources(self, facets: "Facets", out: dict, mode=0, window=None, want_surface=False, fallback=False):
         """out: dict of torch device tensors e1, e2, s1, s2, c12, lmax (f64), argmax, n_above (i32),
         flags (i32 viewed as u32), surface (f64) -- any may be absent except flags."""
-        o = rlf_fit_opts()
-        o.mode = int(mode)
-        o.want_surface = 1 if want_surface else 0
-        o.window = _ptr(window)
-        o.fallback = 1 if fallback else 0
-        o.reserved = 0
-        r = rlf_fit_out()
-        for k in ("e1", "e2", "s1", "s2", "c12", "lmax", "argmax", "n_above", "flags", "surface"):
-            setattr(r, k, _ptr(out.get(k)))
+        o, r = _fit_structs(out, mode, window, want_surface, fallback)
         return self._check(lib().rlf_fit_sources(self.h, facets.h, ctypes.byref(o), ctypes.byref(r)))
+
+    def pass_create(self, obs: Obs, cat, facets: "Facets", out: dict, tune_path=None, mode=0, window=None,
+                    want_surface=False, fallback=False, prior_mu=None) -> "Pass":
+        o, r = _fit_structs(out, mode, window, want_surface, fallback)
+        ob = obs.c()
+        c, keep = catalog(cat, prior_mu)
+        h = _c_vp()
+        tp = None if tune_path is None else os.fsencode(tune_path)
+        self._check(lib().rlf_pass_create(self.h, ctypes.byref(ob), ctypes.byref(c), facets.h, ctypes.byref(o),
+                                          ctypes.byref(r), tp, ctypes.byref(h)))
+        return Pass(self, h)
+
+
+def _fit_structs(out, mode, window, want_surface, fallback):
+    o = rlf_fit_opts()
+    o.mode = int(mode)
+    o.want_surface = 1 if want_surface else 0
+    o.window = _ptr(window)
+    o.fallback = 1 if fallback else 0
+    o.reserved = 0
+    r = rlf_fit_out()
+    for k in ("e1", "e2", "s1", "s2", "c12", "lmax", "argmax", "n_above", "flags", "surface"):
+        setattr(r, k, _ptr(out.get(k)))
+    return o, r
+
+
+class Pass:
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+
+    def launch(self):
+        return self.ctx._check(lib().rlf_pass_launch(self.h))
+
+    def tiles(self):
+        t = (ctypes.c_int32 * 4)()
+        u = (ctypes.c_int32 * 4)()
+        self.ctx._check(lib().rlf_pass_tiles(self.h, t, u))
+        return list(t), list(u)
+
+    def free(self):
+        if self.h:
+            lib().rlf_pass_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Facets:

@@ -44,6 +44,7 @@ extern "C" {
 typedef struct rlf_ctx rlf_ctx;        /* opaque: device, stream, parameters, tables */
 typedef struct rlf_facets rlf_facets;  /* opaque: facet geometry + device buffers for one catalogue */
 typedef struct rlf_pass rlf_pass;      /* opaque: a captured, replayable pass over all sources */
+typedef struct rlf_mlp rlf_mlp;        /* opaque: the grid-narrowing network and its optimiser state */
 
 typedef enum {
   RLF_OK = 0,
@@ -271,6 +272,60 @@ int rlf_pass_tiles(const rlf_pass *pass, int32_t *tiles /*[4]*/, int32_t *tuned 
 
 /* Free a pass (NULL is a no-op); synchronises. */
 int rlf_pass_free(rlf_pass *pass);
+
+/* ---- Grid-narrowing network (not in the paper) --------------------------
+ * An MLP maps a facet to (e1, e2, ln alpha) and their log-variances; its
+ * predictions centre narrowed ellipticity windows for rlf_fit_sources
+ * (mode 1 with fallback), the full-grid fit staying the judge.
+ *   input   8192 values: the facet's cells with -32 <= ix, iy <= 31, Vbar / S
+ *           (S the catalogue flux), Re at (iy+32)*64 + ix+32, Im at 4096 +
+ *           the same index, 0 for empty cells; BF16 [n x 8192] row-major
+ *   layers  z_l = h_{l-1} W_l + b_l, h_l = GELU(z_l) = z Phi(z) (l = 1..3,
+ *           width 512), y = h_3 W_4 + b_4 (6 outputs, FP32 [n x 6]:
+ *           mu = y[0:3], s = y[3:6] log-variances)
+ *   loss    mean over samples of sum_d (s_d + (t_d - mu_d)^2 exp(-s_d)) / 2
+ * Products are BF16 on MFMA with FP32 accumulation; FP32 master weights,
+ * Adam (0.9, 0.999, 1e-8).  Parameters, FP32, in this order: W1 [8192 x 512],
+ * b1 [512], W2 [512 x 512], b2, W3 [512 x 512], b3, W4 [512 x 6], b4 [6]
+ * (weights row-major, input index slow). */
+
+/* Number of parameters (4,723,206). */
+int64_t rlf_mlp_num_params(void);
+
+/* Create a network with zero parameters that trains on batches of at most
+ * max_batch rows (forward accepts any number of rows). */
+int rlf_mlp_create(rlf_ctx *ctx, int64_t max_batch, rlf_mlp **net);
+
+/* Free a network (NULL is a no-op); synchronises. */
+int rlf_mlp_free(rlf_mlp *net);
+
+/* Set parameters (host, FP32 [n_params]) and the Adam state (host m, v or
+ * NULL for zero; step = updates taken so far).  Synchronises. */
+int rlf_mlp_set_state(rlf_mlp *net, const float *params, const float *adam_m, const float *adam_v, int64_t step);
+
+/* Copy parameters, Adam moments and the last gradients to host arrays
+ * [n_params] (any may be NULL) and the step count.  Synchronises. */
+int rlf_mlp_get_state(rlf_mlp *net, float *params, float *adam_m, float *adam_v, float *grad, int64_t *step);
+
+/* Network inputs of every source of the last extraction: device BF16
+ * [n_src x 8192]. */
+int rlf_mlp_features(rlf_ctx *ctx, const rlf_facets *facets, void *x);
+
+/* y = network(x) for `rows` inputs: x device BF16 [rows x 8192], y device
+ * FP32 [rows x 6]. */
+int rlf_mlp_forward(rlf_mlp *net, const void *x, int64_t rows, float *y);
+
+/* One Adam step on a batch (rows <= max_batch): x device BF16 [rows x 8192],
+ * target device FP32 [rows x 3] (e1, e2, ln alpha), learning rate lr; the
+ * batch loss is written to device *loss (FP64). */
+int rlf_mlp_train_step(rlf_mlp *net, const void *x, const float *target, int64_t rows, float lr, double *loss);
+
+/* Window boxes for rlf_fit_sources mode 1 from predictions y (device FP32
+ * [rows x 6]): per axis, mu +- nsigma exp(s/2), widened to at least
+ * +- min_half grid steps around the nearest grid point, snapped outward and
+ * clamped to the grid; written as device int32 [rows x 4]
+ * (i1lo, i1hi, i2lo, i2hi). */
+int rlf_mlp_windows(rlf_ctx *ctx, const float *y, int64_t rows, double nsigma, int32_t min_half, int32_t *window);
 
 #ifdef __cplusplus
 }

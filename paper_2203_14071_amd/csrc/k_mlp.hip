@@ -1,0 +1,310 @@
+// The grid-narrowing network: features, BF16 MFMA GEMM, epilogues, loss,
+// back-propagation helpers, Adam, and the window boxes.
+//
+// GEMM: C[M x N] (FP32) = A[M x K] * B[K x N], A and B BF16 with arbitrary
+// element strides (so X W, dZ W^T and H^T dZ all use one kernel).  Block tile
+// 128 x 128 x 32, four waves each owning a 64 x 64 quarter as 2 x 2
+// v_mfma_f32_32x32x16_bf16 tiles.  Operand fragments of that instruction:
+// lane l holds A[l%32][8(l/32)+t] and B[8(l/32)+t][l%32] (t = 0..7) and
+// accumulator r of lane l is C[8(r/4) + 4(l/32) + r%4][l%32].  LDS keeps the
+// A tile as [m][k] and the B tile as [n][k] (k contiguous, padded by 8), so
+// each fragment is one 16-byte LDS read.  Global loads take 8 contiguous
+// BF16 when the operand is contiguous along k (or along m / n, transposing
+// into LDS), else single elements; out-of-range elements are zero.
+// grid.z splits K; with more than one split each slice writes its partial
+// product to a workspace and a second kernel adds the slices in a fixed
+// order, so results do not depend on scheduling.
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+
+#include "rlf_internal.h"
+
+namespace rlf {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kPad = 8, kLd = kBK + kPad;
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return __float2bfloat16(x); }
+
+// Stage rows [r0, r0+128) x k [k0, k0+32) of an operand whose element (r, k)
+// is at p[r*sr + k*sk] into lds[r][k]; rows >= nr or k >= nk read as zero.
+__device__ __forceinline__ void stage(__bf16 *lds, const __bf16 *__restrict__ p, int64_t sr, int64_t sk, int r0,
+                                      int nr, int k0, int nk) {
+  const int t = threadIdx.x;
+  if (sk == 1 && (sr % 8) == 0) {
+    // 128 rows x 4 chunks of 8 k: 512 chunks, 2 per thread
+    for (int c = t; c < kBM * (kBK / 8); c += 256) {
+      const int r = c / (kBK / 8), kc = (c % (kBK / 8)) * 8;
+      const int gr = r0 + r, gk = k0 + kc;
+      bf16x8 v;
+      if (gr < nr && gk + 8 <= nk) {
+        v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)gr * sr + gk);
+      } else {
+        for (int e = 0; e < 8; ++e)
+          v[e] = (gr < nr && gk + e < nk) ? p[(int64_t)gr * sr + (int64_t)(gk + e)] : to_bf16(0.0f);
+      }
+      *reinterpret_cast<bf16x8 *>(lds + r * kLd + kc) = v;
+    }
+  } else if (sr == 1 && (sk % 8) == 0) {
+    // contiguous along rows: 32 k x 16 chunks of 8 rows
+    for (int c = t; c < kBK * (kBM / 8); c += 256) {
+      const int k = c / (kBM / 8), rc = (c % (kBM / 8)) * 8;
+      const int gk = k0 + k, gr = r0 + rc;
+      bf16x8 v;
+      if (gk < nk && gr + 8 <= nr) {
+        v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)gk * sk + gr);
+      } else {
+        for (int e = 0; e < 8; ++e)
+          v[e] = (gk < nk && gr + e < nr) ? p[(int64_t)gk * sk + (int64_t)(gr + e)] : to_bf16(0.0f);
+      }
+      for (int e = 0; e < 8; ++e) lds[(rc + e) * kLd + k] = v[e];
+    }
+  } else {
+    for (int c = t; c < kBM * kBK; c += 256) {
+      const int r = c / kBK, k = c % kBK;
+      const int gr = r0 + r, gk = k0 + k;
+      lds[r * kLd + k] = (gr < nr && gk < nk) ? p[(int64_t)gr * sr + (int64_t)gk * sk] : to_bf16(0.0f);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 sa[kBM * kLd];
+  __shared__ __attribute__((aligned(16))) __bf16 sb[kBN * kLd];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+  // K slices start on kBK boundaries so the 16-byte loads stay aligned
+  const int kper = ((g.K + (int)gridDim.z - 1) / (int)gridDim.z + kBK - 1) / kBK * kBK;
+  const int kb = blockIdx.z * kper, ke = min(g.K, kb + kper);
+  f32x16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  for (int k0 = kb; k0 < ke; k0 += kBK) {
+    __syncthreads();
+    // A tile: rows m, elements A(m, k) = a[m*sam + k*sak]; B tile stored [n][k]: B(k, n) = b[k*sbk + n*sbn]
+    stage(sa, g.a, g.sam, g.sak, m0, g.M, k0, ke);
+    stage(sb, g.b, g.sbn, g.sbk, n0, g.N, k0, ke);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 16) {
+      bf16x8 fa[2], fb[2];
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *reinterpret_cast<const bf16x8 *>(sa + (wm + i * 32 + (lane & 31)) * kLd + kk + 8 * (lane >> 5));
+      for (int j = 0; j < 2; ++j)
+        fb[j] = *reinterpret_cast<const bf16x8 *>(sb + (wn + j * 32 + (lane & 31)) * kLd + kk + 8 * (lane >> 5));
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  float *outp = gridDim.z > 1 ? g.ws + (int64_t)blockIdx.z * g.M * g.N : g.c;
+  const int64_t ld = gridDim.z > 1 ? g.N : g.ldc;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn + j * 32 + (lane & 31);
+        if (m < g.M && n < g.N) outp[(int64_t)m * ld + n] = acc[i][j][r];
+      }
+}
+
+// c[m][n] = sum over slices z = 0, 1, ... of ws[z][m][n], in that order
+__global__ __launch_bounds__(256) void k_reduce_split(const float *ws, int split, int M, int N, float *c,
+                                                      int64_t ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    float acc = ws[i];
+    for (int z = 1; z < split; ++z) acc += ws[(int64_t)z * total + i];
+    c[(i / N) * ldc + (i % N)] = acc;
+  }
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// z = c + b; h = GELU(z) (BF16) or, for the output layer, y = z (FP32)
+__global__ __launch_bounds__(256) void k_bias_act(const float *c, const float *b, int64_t rows, int cols, float *z,
+                                                  __bf16 *h, int act) {
+  const int64_t n = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = c[i] + b[i % cols];
+    z[i] = v;
+    if (act) h[i] = to_bf16(gelu(v));
+  }
+}
+
+// Gaussian negative log-likelihood head: y [n x 6] -> loss (added to *loss),
+// dY = dL/dy (FP32 for the bias, BF16 for the products).
+__global__ __launch_bounds__(256) void k_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb,
+                                              double *loss) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      const float mu = y[i * 6 + d], s = y[i * 6 + 3 + d];
+      const float e = t[i * 3 + d] - mu;
+      const float ie = expf(-s);
+      acc += 0.5 * ((double)s + (double)e * e * ie);
+      const float gm = -e * ie / (float)n, gs = 0.5f * (1.0f - e * e * ie) / (float)n;
+      dy[i * 6 + d] = gm;
+      dy[i * 6 + 3 + d] = gs;
+      dyb[i * 6 + d] = to_bf16(gm);
+      dyb[i * 6 + 3 + d] = to_bf16(gs);
+    }
+  }
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) unsafeAtomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n);
+}
+
+// dz = dh * GELU'(z): FP32 (for the bias) and BF16 (for the products)
+__global__ __launch_bounds__(256) void k_gelu_back(const float *dh, const float *z, int64_t n, float *dz,
+                                                   __bf16 *dzb) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = dh[i] * gelu_grad(z[i]);
+    dz[i] = v;
+    dzb[i] = to_bf16(v);
+  }
+}
+
+// db[col] = sum over rows of d[row][col]: one block per column group of 64
+__global__ __launch_bounds__(256) void k_colsum(const float *d, int64_t rows, int cols, float *db) {
+  __shared__ float sh[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;
+  float acc = 0.0f;
+  if (col < cols)
+    for (int64_t r = rg; r < rows; r += 4) acc += d[r * cols + col];
+  sh[rg][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (rg == 0 && col < cols) db[col] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n,
+                                              float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = to_bf16(wi);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float *x, __bf16 *y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = to_bf16(x[i]);
+}
+
+// Network input: facet cells inside -32..31 on both axes, Vbar / S.
+__global__ __launch_bounds__(256) void k_features(FeatureArgs a) {
+  const int s = blockIdx.x;
+  __bf16 *x = a.x + (int64_t)s * 8192;
+  for (int i = threadIdx.x; i < 8192; i += blockDim.x) x[i] = to_bf16(0.0f);
+  __syncthreads();
+  const double inv = 1.0 / a.src[s].flux;
+  for (int64_t c = a.offsets[s] + threadIdx.x; c < a.offsets[s + 1]; c += blockDim.x) {
+    const int ix = a.ix[c], iy = a.iy[c];
+    if (ix < -32 || ix > 31 || iy < -32 || iy > 31) continue;
+    const int pos = (iy + 32) * 64 + (ix + 32);
+    x[pos] = to_bf16((float)(a.vre[c] * inv));
+    x[4096 + pos] = to_bf16((float)(a.vim[c] * inv));
+  }
+}
+
+// Window boxes from the predictions (decided in FP64 from the FP32 outputs).
+__global__ __launch_bounds__(256) void k_windows(const float *y, int64_t n, double nsigma, int n_e, double step,
+                                                 int min_half, int32_t *win) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (n_e - 1) / 2;
+  for (int d = 0; d < 2; ++d) {
+    const double mu = (double)y[i * 6 + d];
+    const double sd = exp(0.5 * (double)y[i * 6 + 3 + d]);
+    int lo = (int)floor((mu - nsigma * sd) / step + c);
+    int hi = (int)ceil((mu + nsigma * sd) / step + c);
+    const int mid = (int)rint(mu / step + c);
+    lo = min(lo, mid - min_half);
+    hi = max(hi, mid + min_half);
+    win[i * 4 + 2 * d] = min(max(lo, 0), n_e - 1);
+    win[i * 4 + 2 * d + 1] = min(max(hi, 0), n_e - 1);
+  }
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs &g, int split_k, hipStream_t st) {
+  if (split_k > 1 && (!g.ws || (int64_t)split_k * g.M * g.N > g.ws_floats)) return hipErrorInvalidValue;
+  const dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, split_k > 1 ? split_k : 1);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+  if (split_k > 1)
+    hipLaunchKernelGGL(k_reduce_split, dim3(grid_for((int64_t)g.M * g.N)), dim3(256), 0, st, g.ws, split_k, g.M, g.N,
+                       g.c, g.ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int cols, float *z, __bf16 *h, int act,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_bias_act, dim3(grid_for(rows * cols)), dim3(256), 0, st, c, b, rows, cols, z, h, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_head, dim3(grid_for(n)), dim3(256), 0, st, y, t, n, dy, dyb, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *dz, __bf16 *dzb, hipStream_t st) {
+  hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(n)), dim3(256), 0, st, dh, z, n, dz, dzb);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64), dim3(256), 0, st, d, rows, cols, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n, float lr, int64_t step,
+                       hipStream_t st) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)step)), c2 = (float)(1.0 - std::pow(0.999, (double)step));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, st, w, wb, g, m, v, n, lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const FeatureArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3(a.n_src), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half, int32_t *win,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_windows, dim3(grid_for(n)), dim3(256), 0, st, y, n, nsigma, n_e, step, min_half, win);
+  return hipGetLastError();
+}
+
+}  // namespace rlf

@@ -180,6 +180,29 @@ struct EstimateArgs {
   double *surface;           // [n_src*n_e*n_e] or null
 };
 
+// C[M x N] (FP32, row stride ldc) = A * B, A(m, k) = a[m*sam + k*sak],
+// B(k, n) = b[k*sbk + n*sbn], both BF16.
+struct GemmArgs {
+  const __bf16 *a;
+  int64_t sam, sak;
+  const __bf16 *b;
+  int64_t sbk, sbn;
+  float *c;
+  int64_t ldc;
+  int32_t M, N, K;
+  float *ws;                 // split-K partials [split x M x N]
+  int64_t ws_floats;
+};
+
+struct FeatureArgs {
+  int32_t n_src;
+  const int64_t *offsets;
+  const int32_t *ix, *iy;
+  const double *vre, *vim;
+  const SrcModel *src;
+  __bf16 *x;                 // [n_src * 8192]
+};
+
 // Launchers (enqueue on `st`; return the launch status).
 hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st);
 hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st);
@@ -198,5 +221,18 @@ hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
+hipError_t launch_gemm(const GemmArgs &g, int split_k, hipStream_t st);
+hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int cols, float *z, __bf16 *h, int act,
+                           hipStream_t st);
+hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
+                       hipStream_t st);
+hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *dz, __bf16 *dzb, hipStream_t st);
+hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, hipStream_t st);
+hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n, float lr, int64_t step,
+                       hipStream_t st);
+hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);
+hipError_t launch_features(const FeatureArgs &a, hipStream_t st);
+hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half, int32_t *win,
+                          hipStream_t st);
 
 }  // namespace rlf

@@ -1,0 +1,276 @@
+// Grid-narrowing network: parameters (FP32 master + BF16 copies), Adam state,
+// activation buffers, and the forward / training / window entry points.
+// Parameter layout (FP32, contiguous): W1 [8192 x 512], b1 [512],
+// W2 [512 x 512], b2, W3 [512 x 512], b3, W4 [512 x 6], b4 [6].
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rlf_objects.h"
+
+namespace {
+
+constexpr int kIn = 8192, kHid = 512, kOut = 6;
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kIn * kHid;
+constexpr int64_t kOffW2 = kOffB1 + kHid;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kHid * kHid;
+constexpr int64_t kOffW3 = kOffB2 + kHid;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kHid * kHid;
+constexpr int64_t kOffW4 = kOffB3 + kHid;
+constexpr int64_t kOffB4 = kOffW4 + (int64_t)kHid * kOut;
+constexpr int64_t kParams = kOffB4 + kOut;
+
+}  // namespace
+
+struct rlf_mlp {
+  rlf_ctx *c = nullptr;
+  int64_t max_batch = 0;
+  int64_t step = 0;
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  __bf16 *wb = nullptr;
+  float *z[3] = {nullptr, nullptr, nullptr};
+  __bf16 *h[3] = {nullptr, nullptr, nullptr};
+  float *y = nullptr, *cbuf = nullptr, *dy = nullptr, *dh = nullptr, *dz = nullptr;
+  float *ws = nullptr;                       // split-K partial products
+  __bf16 *dyb = nullptr, *dzb = nullptr;
+};
+
+namespace {
+
+using rlf::dalloc;
+using rlf::dfree;
+using rlf::fail;
+using rlf::hip_fail;
+
+void mlp_release(rlf_mlp *n) {
+  dfree(n->w);
+  dfree(n->m);
+  dfree(n->v);
+  dfree(n->g);
+  dfree(n->wb);
+  for (int l = 0; l < 3; ++l) {
+    dfree(n->z[l]);
+    dfree(n->h[l]);
+  }
+  dfree(n->y);
+  dfree(n->cbuf);
+  dfree(n->dy);
+  dfree(n->dh);
+  dfree(n->dz);
+  dfree(n->dyb);
+  dfree(n->dzb);
+  dfree(n->ws);
+}
+
+constexpr int kMaxSplitBlocks = 512;                  // tiles x K slices
+constexpr int64_t kWsFloats = (int64_t)kMaxSplitBlocks * 128 * 128;
+
+int split_for(int M, int N, int K) {
+  const int tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  int s = 1;
+  while (tiles * s * 2 <= kMaxSplitBlocks && K / (s * 2) >= 64) s *= 2;
+  return s;
+}
+
+// C[M x N] = A * B with element strides (see GemmArgs).
+int gemm(rlf_mlp *net, const __bf16 *a, int64_t sam, int64_t sak, const __bf16 *b, int64_t sbk, int64_t sbn,
+         float *out, int M, int N, int K) {
+  rlf_ctx *c = net->c;
+  GemmArgs ga{};
+  ga.a = a;
+  ga.sam = sam;
+  ga.sak = sak;
+  ga.b = b;
+  ga.sbk = sbk;
+  ga.sbn = sbn;
+  ga.c = out;
+  ga.ldc = N;
+  ga.M = M;
+  ga.N = N;
+  ga.K = K;
+  ga.ws = net->ws;
+  ga.ws_floats = kWsFloats;
+  hipError_t e = launch_gemm(ga, split_for(M, N, K), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "gemm launch");
+  return RLF_OK;
+}
+
+// Forward of rows [0, nb) of x into the layer buffers; y_out receives the outputs.
+int forward_chunk(rlf_mlp *n, const __bf16 *x, int nb, float *y_out) {
+  rlf_ctx *c = n->c;
+  const __bf16 *hin = x;
+  int kin = kIn;
+  const int64_t offW[3] = {kOffW1, kOffW2, kOffW3}, offB[3] = {kOffB1, kOffB2, kOffB3};
+  for (int l = 0; l < 3; ++l) {
+    if (int e = gemm(n, hin, kin, 1, n->wb + offW[l], kHid, 1, n->cbuf, nb, kHid, kin)) return e;
+    hipError_t e = launch_bias_act(n->cbuf, n->w + offB[l], nb, kHid, n->z[l], n->h[l], 1, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "bias/GELU launch");
+    hin = n->h[l];
+    kin = kHid;
+  }
+  if (int e = gemm(n, hin, kHid, 1, n->wb + kOffW4, kOut, 1, n->cbuf, nb, kOut, kHid)) return e;
+  hipError_t e = launch_bias_act(n->cbuf, n->w + kOffB4, nb, kOut, y_out, nullptr, 0, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "output bias launch");
+  return RLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t rlf_mlp_num_params(void) { return kParams; }
+
+int rlf_mlp_create(rlf_ctx *c, int64_t max_batch, rlf_mlp **out) {
+  if (!c) return RLF_EINVAL;
+  if (!out || max_batch < 1 || max_batch > (1 << 20)) return fail(c, RLF_EINVAL, "rlf_mlp_create: max_batch");
+  HIPCHK(c, hipSetDevice(c->device));
+  rlf_mlp *n = new (std::nothrow) rlf_mlp();
+  if (!n) return fail(c, RLF_ENOMEM, "host allocation");
+  n->c = c;
+  n->max_batch = max_batch;
+  const int64_t B = max_batch;
+  int rc = RLF_OK;
+  do {
+    if ((rc = dalloc(c, &n->w, kParams))) break;
+    if ((rc = dalloc(c, &n->m, kParams))) break;
+    if ((rc = dalloc(c, &n->v, kParams))) break;
+    if ((rc = dalloc(c, &n->g, kParams))) break;
+    if ((rc = dalloc(c, &n->wb, kParams))) break;
+    for (int l = 0; l < 3 && rc == RLF_OK; ++l) {
+      if ((rc = dalloc(c, &n->z[l], B * kHid))) break;
+      rc = dalloc(c, &n->h[l], B * kHid);
+    }
+    if (rc) break;
+    if ((rc = dalloc(c, &n->y, B * kOut))) break;
+    if ((rc = dalloc(c, &n->cbuf, B * kHid))) break;
+    if ((rc = dalloc(c, &n->dy, B * kOut))) break;
+    if ((rc = dalloc(c, &n->dyb, B * kOut))) break;
+    if ((rc = dalloc(c, &n->dh, B * kHid))) break;
+    if ((rc = dalloc(c, &n->dz, B * kHid))) break;
+    if ((rc = dalloc(c, &n->dzb, B * kHid))) break;
+    if ((rc = dalloc(c, &n->ws, kWsFloats))) break;
+    hipError_t e = hipMemset(n->w, 0, sizeof(float) * kParams);
+    if (e == hipSuccess) e = hipMemset(n->m, 0, sizeof(float) * kParams);
+    if (e == hipSuccess) e = hipMemset(n->v, 0, sizeof(float) * kParams);
+    if (e == hipSuccess) e = hipMemset(n->wb, 0, sizeof(__bf16) * kParams);
+    if (e != hipSuccess) rc = hip_fail(c, e, "rlf_mlp_create: clearing parameters");
+  } while (0);
+  if (rc) {
+    mlp_release(n);
+    delete n;
+    return rc;
+  }
+  *out = n;
+  return RLF_OK;
+}
+
+int rlf_mlp_free(rlf_mlp *n) {
+  if (!n) return RLF_OK;
+  (void)hipSetDevice(n->c->device);
+  (void)hipStreamSynchronize(n->c->stream);
+  mlp_release(n);
+  delete n;
+  return RLF_OK;
+}
+
+int rlf_mlp_set_state(rlf_mlp *n, const float *params_host, const float *m_host, const float *v_host, int64_t step) {
+  if (!n || !params_host || step < 0) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(n->w, params_host, sizeof(float) * kParams, hipMemcpyHostToDevice));
+  if (m_host) HIPCHK(c, hipMemcpy(n->m, m_host, sizeof(float) * kParams, hipMemcpyHostToDevice));
+  else HIPCHK(c, hipMemset(n->m, 0, sizeof(float) * kParams));
+  if (v_host) HIPCHK(c, hipMemcpy(n->v, v_host, sizeof(float) * kParams, hipMemcpyHostToDevice));
+  else HIPCHK(c, hipMemset(n->v, 0, sizeof(float) * kParams));
+  n->step = step;
+  HIPCHK(c, launch_to_bf16(n->w, n->wb, kParams, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RLF_OK;
+}
+
+int rlf_mlp_get_state(rlf_mlp *n, float *params_host, float *m_host, float *v_host, float *grad_host, int64_t *step) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (params_host) HIPCHK(c, hipMemcpy(params_host, n->w, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (m_host) HIPCHK(c, hipMemcpy(m_host, n->m, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (v_host) HIPCHK(c, hipMemcpy(v_host, n->v, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (grad_host) HIPCHK(c, hipMemcpy(grad_host, n->g, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (step) *step = n->step;
+  return RLF_OK;
+}
+
+int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {
+  if (!c) return RLF_EINVAL;
+  if (!f || f->ctx != c || !x) return fail(c, RLF_EINVAL, "rlf_mlp_features: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  FeatureArgs a{};
+  a.n_src = (int32_t)f->n_src;
+  a.offsets = f->cells.offsets;
+  a.ix = f->cells.ix;
+  a.iy = f->cells.iy;
+  a.vre = f->cells.vre;
+  a.vim = f->cells.vim;
+  a.src = f->d_src;
+  a.x = reinterpret_cast<__bf16 *>(x);
+  HIPCHK(c, launch_features(a, c->stream));
+  return RLF_OK;
+}
+
+int rlf_mlp_forward(rlf_mlp *n, const void *x, int64_t rows, float *y) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  if (!x || !y || rows < 1) return fail(c, RLF_EINVAL, "rlf_mlp_forward: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  const __bf16 *xb = reinterpret_cast<const __bf16 *>(x);
+  for (int64_t r0 = 0; r0 < rows; r0 += n->max_batch) {
+    const int nb = (int)std::min<int64_t>(n->max_batch, rows - r0);
+    if (int e = forward_chunk(n, xb + r0 * kIn, nb, y + r0 * kOut)) return e;
+  }
+  return RLF_OK;
+}
+
+int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t rows, float lr, double *loss) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  if (!x || !target || !loss || rows < 1 || rows > n->max_batch || !(lr >= 0))
+    return fail(c, RLF_EINVAL, "rlf_mlp_train_step: arguments (rows must be <= max_batch)");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nb = (int)rows;
+  const __bf16 *xb = reinterpret_cast<const __bf16 *>(x);
+  if (int e = forward_chunk(n, xb, nb, n->y)) return e;
+  HIPCHK(c, launch_fill_f64(loss, 1, 0.0, c->stream));
+  HIPCHK(c, launch_head(n->y, target, nb, n->dy, n->dyb, loss, c->stream));
+  // output layer: dW4 = h3^T dY, db4 = sum dY, dh3 = dY W4^T
+  if (int e = gemm(n, n->h[2], 1, kHid, n->dyb, kOut, 1, n->g + kOffW4, kHid, kOut, nb)) return e;
+  HIPCHK(c, launch_colsum(n->dy, nb, kOut, n->g + kOffB4, c->stream));
+  if (int e = gemm(n, n->dyb, kOut, 1, n->wb + kOffW4, 1, kOut, n->dh, nb, kHid, kOut)) return e;
+  const int64_t offW[3] = {kOffW1, kOffW2, kOffW3}, offB[3] = {kOffB1, kOffB2, kOffB3};
+  for (int l = 2; l >= 0; --l) {
+    HIPCHK(c, launch_gelu_back(n->dh, n->z[l], (int64_t)nb * kHid, n->dz, n->dzb, c->stream));
+    HIPCHK(c, launch_colsum(n->dz, nb, kHid, n->g + offB[l], c->stream));
+    const __bf16 *hin = l == 0 ? xb : n->h[l - 1];
+    const int kin = l == 0 ? kIn : kHid;
+    if (int e = gemm(n, hin, 1, kin, n->dzb, kHid, 1, n->g + offW[l], kin, kHid, nb)) return e;
+    if (l > 0)
+      if (int e = gemm(n, n->dzb, kHid, 1, n->wb + offW[l], 1, kHid, n->dh, nb, kHid, kHid)) return e;
+  }
+  n->step += 1;
+  HIPCHK(c, launch_adam(n->w, n->wb, n->g, n->m, n->v, kParams, lr, n->step, c->stream));
+  return RLF_OK;
+}
+
+int rlf_mlp_windows(rlf_ctx *c, const float *y, int64_t rows, double nsigma, int32_t min_half, int32_t *window) {
+  if (!c) return RLF_EINVAL;
+  if (!y || !window || rows < 1 || !(nsigma > 0) || min_half < 0)
+    return fail(c, RLF_EINVAL, "rlf_mlp_windows: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_windows(y, rows, nsigma, c->p.n_e, c->p.e_step, min_half, window, c->stream));
+  return RLF_OK;
+}
+
+}  // extern "C"

@@ -82,6 +82,15 @@ _SIGNATURES = {
     "rlf_pass_launch": ([_c_vp], ctypes.c_int),
     "rlf_pass_tiles": ([_c_vp, _c_ip, _c_ip], ctypes.c_int),
     "rlf_pass_free": ([_c_vp], ctypes.c_int),
+    "rlf_mlp_num_params": ([], ctypes.c_int64),
+    "rlf_mlp_create": ([_c_vp, ctypes.c_int64, ctypes.POINTER(_c_vp)], ctypes.c_int),
+    "rlf_mlp_free": ([_c_vp], ctypes.c_int),
+    "rlf_mlp_set_state": ([_c_vp, _c_vp, _c_vp, _c_vp, ctypes.c_int64], ctypes.c_int),
+    "rlf_mlp_get_state": ([_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_lp], ctypes.c_int),
+    "rlf_mlp_features": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
+    "rlf_mlp_forward": ([_c_vp, _c_vp, ctypes.c_int64, _c_vp], ctypes.c_int),
+    "rlf_mlp_train_step": ([_c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_float, _c_vp], ctypes.c_int),
+    "rlf_mlp_windows": ([_c_vp, _c_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _c_vp], ctypes.c_int),
 }
 
 _lib = None
@@ -310,6 +319,61 @@ class Facets:
                                               ix.ctypes.data_as(_c_ip), iy.ctypes.data_as(_c_ip),
                                               cnt.ctypes.data_as(_c_ip), _dp(ws), _dp(vb), _dp(th)))
         return dict(offsets=off, ix=ix, iy=iy, count=cnt, wsum=ws, vbar=vb[0::2] + 1j * vb[1::2], theta=th)
+
+
+def _np_ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Mlp:
+    """The grid-narrowing network (rlf_mlp_*); tensors are torch device tensors."""
+
+    def __init__(self, ctx: Context, max_batch=512):
+        self.ctx = ctx
+        h = _c_vp()
+        ctx._check(lib().rlf_mlp_create(ctx.h, int(max_batch), ctypes.byref(h)))
+        self.h = h
+        self.n_params = int(lib().rlf_mlp_num_params())
+
+    def free(self):
+        if self.h:
+            lib().rlf_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def set_state(self, params, m=None, v=None, step=0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        mm = None if m is None else np.ascontiguousarray(m, dtype=np.float32)
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float32)
+        assert p.size == self.n_params
+        self.ctx._check(lib().rlf_mlp_set_state(self.h, _np_ptr(p), _np_ptr(mm), _np_ptr(vv), int(step)))
+
+    def get_state(self):
+        out = {k: np.zeros(self.n_params, np.float32) for k in ("params", "m", "v", "grad")}
+        st = ctypes.c_int64()
+        self.ctx._check(lib().rlf_mlp_get_state(self.h, _np_ptr(out["params"]), _np_ptr(out["m"]),
+                                                _np_ptr(out["v"]), _np_ptr(out["grad"]), ctypes.byref(st)))
+        out["step"] = st.value
+        return out
+
+    def features(self, facets: "Facets", x):
+        return self.ctx._check(lib().rlf_mlp_features(self.ctx.h, facets.h, _ptr(x)))
+
+    def forward(self, x, y):
+        return self.ctx._check(lib().rlf_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)))
+
+    def train_step(self, x, target, lr, loss):
+        return self.ctx._check(lib().rlf_mlp_train_step(self.h, _ptr(x), _ptr(target), int(x.shape[0]),
+                                                        float(lr), _ptr(loss)))
+
+    def windows(self, y, window, nsigma=3.0, min_half=3):
+        return self.ctx._check(lib().rlf_mlp_windows(self.ctx.h, _ptr(y), int(y.shape[0]), float(nsigma),
+                                                     int(min_half), _ptr(window)))
 
 
 def alpha_from_flux(flux_jy, add=-0.93, esp=0.33):

@@ -1,0 +1,174 @@
+"""The grid-narrowing network's HIP kernels (BF16 MFMA GEMMs, epilogues,
+loss, back-propagation, Adam, features, windows) against the FP64 network
+oracle with BF16 rounding at the same places.
+
+Tolerances: both sides multiply the same BF16 operands; the kernels
+accumulate in FP32 (relative error ~ sqrt(K) 2^-24 per sum, K <= 8192) and
+round activations / gradients to BF16 from FP32 values that differ from the
+oracle's FP64 values in the last FP32 bits, which moves a small fraction of
+roundings by one BF16 step (2^-8 relative).  Outputs and gradient blocks are
+therefore compared in relative L2 norm (1e-3), and the fraction of elements
+off by more than a few BF16 steps is bounded."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as M
+from paper_2203_14071_amd import rlf, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _init(seed):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for k, s in M.SHAPES:
+        if len(s) == 2:
+            p[k] = rng.standard_normal(s) * math.sqrt(2.0 / s[0])
+        else:
+            p[k] = rng.standard_normal(s) * 0.05
+        p[k] = p[k].astype(np.float32).astype(np.float64)
+    return p
+
+
+def _bf16_tensor(x):
+    torch = G.torch_cuda()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return rlf.Context(0)
+
+
+def test_forward_matches_oracle(ctx):
+    torch = G.torch_cuda()
+    p = _init(7)
+    rng = np.random.default_rng(8)
+    n = 300                                    # ragged against 128-row tiles
+    x = M.bf16(rng.standard_normal((n, M.N_IN)) * 0.2)
+    net = rlf.Mlp(ctx, max_batch=128)          # forward runs in chunks of 128 rows
+    net.set_state(M.pack(p))
+    y = torch.empty((n, 6), dtype=torch.float32, device="cuda:0")
+    net.forward(_bf16_tensor(x), y)
+    ctx.sync()
+    ref, _ = M.forward(x, p)
+    got = y.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref) < 1e-3, _rel(got, ref)
+    assert np.median(np.abs(got - ref)) < 1e-4 * np.median(np.abs(ref)) + 1e-6
+    net.free()
+
+
+def test_train_step_gradients_and_adam_match_oracle(ctx):
+    torch = G.torch_cuda()
+    p = _init(9)
+    rng = np.random.default_rng(10)
+    n = 200
+    x = M.bf16(rng.standard_normal((n, M.N_IN)) * 0.2)
+    t = rng.standard_normal((n, 3)) * 0.3
+    net = rlf.Mlp(ctx, max_batch=256)
+    net.set_state(M.pack(p))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    tt = torch.from_numpy(t.astype(np.float32)).to("cuda:0")
+    lr = 1e-3
+    net.train_step(_bf16_tensor(x), tt, lr, loss)
+    ctx.sync()
+    st = net.get_state()
+    y, cache = M.forward(x, p)
+    t32 = t.astype(np.float32).astype(np.float64)
+    assert loss.item() == pytest.approx(M.loss(y, t32), rel=1e-4)
+    g = M.backward(p, cache, t32)
+    gg = M.unpack(st["grad"])
+    for k, _ in M.SHAPES:
+        assert _rel(gg[k], g[k]) < 2e-3, (k, _rel(gg[k], g[k]))
+    # Adam's first step moves every weight by lr * g / |g| (= +-lr up to eps)
+    zero = {k: np.zeros_like(v) for k, v in p.items()}
+    pn, mn, vn = M.adam(p, g, zero, zero, 1, lr)
+    new = M.unpack(st["params"])
+    for k, _ in M.SHAPES:
+        d = np.abs(new[k] - pn[k])
+        assert np.mean(d > 1e-6) < 1e-2, k           # only tiny-gradient entries may differ in sign
+    assert st["step"] == 1
+    net.free()
+
+
+def test_windows_match_oracle(ctx):
+    torch = G.torch_cuda()
+    rng = np.random.default_rng(11)
+    y = np.zeros((500, 6))
+    y[:, :2] = rng.uniform(-0.85, 0.85, (500, 2))
+    y[:, 3:5] = np.log(rng.uniform(0.005, 0.2, (500, 2)) ** 2)
+    y = y.astype(np.float32).astype(np.float64)
+    yd = torch.from_numpy(y.astype(np.float32)).to("cuda:0")
+    w = torch.empty((500, 4), dtype=torch.int32, device="cuda:0")
+    net = rlf.Mlp(ctx, max_batch=8)
+    net.windows(yd, w, nsigma=3.0, min_half=3)
+    ctx.sync()
+    assert np.array_equal(w.cpu().numpy(), M.windows(y, 3.0, 81, 0.02, 3))
+    net.free()
+
+
+def test_features_match_oracle_facets(ctx):
+    torch = G.torch_cuda()
+    cfg = synth.CONFIGS[0]
+    o = synth.observation(0)
+    cat = synth.catalogue(cfg, synth.rng(0, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(0, synth.STREAM_NOISE), o.n_rows)
+    obs = G.make_obs(o, nz)
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    x = torch.empty((cat.n_src, M.N_IN), dtype=torch.bfloat16, device="cuda:0")
+    net = rlf.Mlp(ctx, max_batch=8)
+    net.features(f, x)
+    ctx.sync()
+    got = x.to(torch.float32).cpu().numpy().astype(np.float64)
+    for s in range(cat.n_src):
+        fac = G.oracle_facet(o, nz, cat, s)
+        ref = M.bf16(M.features(fac.ix, fac.iy, fac.vbar, cat.flux_jy[s]))
+        assert np.mean(got[s] != ref) < 1e-3, s      # BF16 ties of values equal to ~1e-12 may round apart
+        assert np.max(np.abs(got[s] - ref)) <= 2 ** -7 * np.max(np.abs(ref))
+    net.free()
+    f.free()
+
+
+def test_training_reduces_loss_and_resumes_bit_exactly(ctx):
+    torch = G.torch_cuda()
+    rng = np.random.default_rng(12)
+    n = 1024
+    t = rng.standard_normal((n, 3)) * 0.3
+    # inputs carrying the targets (a learnable map)
+    proj = rng.standard_normal((3, M.N_IN)) * 0.05
+    x = M.bf16(t @ proj + 0.01 * rng.standard_normal((n, M.N_IN)))
+    xd = _bf16_tensor(x)
+    td = torch.from_numpy(t.astype(np.float32)).to("cuda:0")
+    p = _init(13)
+    net = rlf.Mlp(ctx, max_batch=256)
+    net.set_state(M.pack(p))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    losses = []
+    for step in range(60):
+        b = (step % 4) * 256
+        net.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss)
+        ctx.sync()
+        losses.append(loss.item())
+    assert np.mean(losses[-8:]) < np.mean(losses[:8]) - 0.5, (losses[:4], losses[-4:])
+    # checkpoint after 60 steps, continue two copies for 5 steps: identical bits
+    st = net.get_state()
+    net2 = rlf.Mlp(ctx, max_batch=256)
+    net2.set_state(st["params"], st["m"], st["v"], st["step"])
+    for step in range(5):
+        b = (step % 4) * 256
+        net.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss)
+        net2.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss)
+    a, c = net.get_state(), net2.get_state()
+    assert np.array_equal(a["params"], c["params"]) and np.array_equal(a["m"], c["m"])
+    assert a["step"] == c["step"] == 65
+    net.free()
+    net2.free()

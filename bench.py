@@ -72,6 +72,10 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=4, help="sources in the oracle baseline sample (0 = skip)")
     ap.add_argument("--only", action="store_true", help="time only the --precision form (for profiling)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the config-3 batched / surrogate block")
+    ap.add_argument("--train-sources", type=int, default=200_000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--nsigma", default="3,4", help="window half-widths (in predicted sigmas) to compare")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -109,11 +113,125 @@ def main():
         "max_abs_de_vs_" + args.precision: float(de),
         "note": "same synthetic field; the mixed form takes complex64 visibilities and f32 weights",
     }
+    if not args.no_surrogate:
+        res["batched_and_surrogate"] = run_surrogate(max(3, args.steps // 3), args.train_sources, args.epochs,
+                                                     [float(v) for v in args.nsigma.split(",")])
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} sources")
         res["cpu_baseline"] = cpu_baseline(main_form["obs_host"], None, main_form["cat"], args.cpu_sample,
                                            oracle.Params())
     print(json.dumps(res), flush=True)
+
+
+def run_surrogate(steps, n_train, epochs, nsigmas):
+    """Config 3 (10,000 sources, 8 channels, mixed form): the captured batched
+    pass, and the full-grid fit against the network-narrowed fit (network
+    trained here on facets simulated from config 1), the full grid judging
+    the narrowed result."""
+    import torch
+
+    from paper_2203_14071_amd import rlf, surrogate, synth
+
+    stream = torch.cuda.current_stream()
+    ctx = rlf.Context(0, stream.cuda_stream, rlf.params(precision=rlf.RLF_MIXED))
+    net = rlf.Mlp(ctx, 512)
+    net.set_state(surrogate.init_params())
+    t0 = time.perf_counter()
+    x, tg = surrogate.training_set(ctx, net, n_train, 20_000, log=log)
+    t_sim = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = surrogate.train(ctx, net, x, tg, epochs, log=log)
+    t_train = time.perf_counter() - t0
+    del x, tg
+    torch.cuda.empty_cache()
+
+    cfg = synth.CONFIGS[3]
+    o = synth.observation(3)
+    cat = synth.catalogue(cfg, synth.rng(3, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(3, synth.STREAM_NOISE), o.n_rows * o.n_chan)
+    dev = "cuda:0"
+    t = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
+    obs = rlf.Obs(t(o.u_m), t(o.v_m), t(o.w_m), o.freq_hz, t(nz, torch.complex64), t(o.weight, torch.float32))
+    ctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
+    catc = cat.with_shape(np.zeros(cat.n_src), np.zeros(cat.n_src))
+    n = cat.n_src
+    f = ctx.facets_create(obs, catc)
+
+    def outs():
+        d = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("e1", "e2", "s1", "s2", "c12", "lmax")}
+        for k in ("argmax", "n_above", "flags"):
+            d[k] = torch.empty(n, dtype=torch.int32, device=dev)
+        return d
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    full = outs()
+    t_ext = timed(lambda: ctx.extract_facets(obs, catc, None, f))
+    t_full = timed(lambda: ctx.fit_sources(f, full))
+    a = {k: v.cpu().numpy() for k, v in full.items()}
+    fit_rms = float(np.sqrt(np.nanmean((a["e1"] - cat.e1) ** 2 + (a["e2"] - cat.e2) ** 2) / 2))
+    win = surrogate.Windowed(ctx, net, n)
+    narrowed = []
+    for ns in nsigmas:
+        nar = outs()
+        t_nar = timed(lambda: win.fit(f, nar, nsigma=ns))
+        b = {k: v.cpu().numpy() for k, v in nar.items()}
+        ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
+        de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
+        w = win.win.cpu().numpy()
+        area = (w[:, 1] - w[:, 0] + 1) * (w[:, 3] - w[:, 2] + 1)
+        y = win.y.cpu().numpy()
+        pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
+        rms = float(np.sqrt(np.mean(de ** 2)))
+        fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
+        log(f"[bench] config 3, nsigma {ns}: narrowed fit {t_nar:.2f} ms (full {t_full:.2f} ms); "
+            f"RMS(de) {rms:.2e}; fallback {fb:.3f}; window {area.mean():.0f} points")
+        narrowed.append({"nsigma": ns, "fit_ms": round(t_nar, 3), "fit_sources_per_s": round(n / (t_nar * 1e-3), 1),
+                         "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
+                         "fit_speedup_vs_plain": round(t_full / t_nar, 3),
+                         "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                         "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
+                         "mean_window_points": round(float(area.mean()), 1),
+                         "network_rms_e_vs_true": round(pred_rms, 4)})
+
+    # the captured batched pass (residual + extraction + queue likelihood + estimate)
+    out_p = outs()
+    ps = ctx.pass_create(obs, catc, f, out_p)
+    tiles, tuned = ps.tiles()
+    t_pass = timed(ps.launch)
+    ps.free()
+    cells = np.diff(f.copy()["offsets"])
+    f.free()
+    log(f"[bench] config 3: extract {t_ext:.2f} ms, full fit {t_full:.2f} ms, captured pass {t_pass:.2f} ms")
+    res = {
+        "workload": f"{cfg.name}: {cfg.n_ant} antennas, {o.n_rows} rows x {o.n_chan} channels, "
+                    f"{n} sources, mixed form",
+        "facet_cells": {"min": int(cells.min()), "mean": round(float(cells.mean()), 1), "max": int(cells.max())},
+        "batched_pass": {"ms_per_pass": round(t_pass, 3), "sources_per_s": round(n / (t_pass * 1e-3), 1),
+                         "queue_tiles_per_bucket": list(tiles), "tiles_from_tuning": list(tuned),
+                         "gvis_per_s": round(o.n_rows * o.n_chan * n / (t_pass * 1e-3) / 1e9, 1)},
+        "plain": {"extract_ms": round(t_ext, 3), "fit_ms": round(t_full, 3),
+                  "fit_sources_per_s": round(n / (t_full * 1e-3), 1),
+                  "end_to_end_sources_per_s": round(n / ((t_ext + t_full) * 1e-3), 1),
+                  "rms_e_vs_true": round(fit_rms, 4)},
+        "surrogate": narrowed,
+        "training": {"sources": n_train, "epochs": epochs, "simulate_s": round(t_sim, 2),
+                     "train_s": round(t_train, 2), "loss_per_epoch": [round(h, 4) for h in hist]},
+    }
+    net.free()
+    ctx.close()
+    del obs
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_form(precision, steps, warmup):

@@ -213,7 +213,8 @@ typedef struct {
   int32_t want_surface;    /* nonzero: write out->surface                                    */
   const int32_t *window;   /* device [n_src*4] inclusive (i1lo, i1hi, i2lo, i2hi) grid boxes */
   int32_t fallback;        /* windowed mode: nonzero = refit on the full grid every source
-                              whose maximum lies on a window edge that is not the domain edge */
+                              whose maximum, or any member of its thresholded set, lies on a
+                              window edge that is not the domain edge */
   int32_t reserved;        /* must be 0 */
 } rlf_fit_opts;
 

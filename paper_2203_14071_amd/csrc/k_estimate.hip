@@ -39,6 +39,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
   __shared__ double shd[4];
   __shared__ double shv[4];
   __shared__ int shi[4];
+  __shared__ int touch;
   const int s = blockIdx.x;
   if (a.redo && !a.redo[s]) return;
   const double *L = a.lsurf + (int64_t)s * a.n_valid;
@@ -112,20 +113,32 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
       if (a.argmax) a.argmax[s] = -1;
       if (a.n_above) a.n_above[s] = 0;
       a.flags[s] = (uint32_t)RLF_FLAG_EMPTY | extra;
-      if (a.redo_out) a.redo_out[s] = 0;
+      // a window holding no valid grid point of a non-empty facet is refitted
+      if (a.redo_out) a.redo_out[s] = n_cells > 0 ? 1 : 0;
     }
     return;
   }
 
-  // pass 2: weight, first moments, count over the thresholded set
+  // pass 2: weight, first moments, count over the thresholded set; with a
+  // window, also whether any member has a grid neighbour outside the window
+  // (the set may continue beyond it: the narrowed result is not trusted)
   const double thr = best + a.log_frac;
   double sw = 0.0, s1 = 0.0, s2 = 0.0, cnt = 0.0;
+  if (threadIdx.x == 0) touch = 0;
+  __syncthreads();
   for (int j = threadIdx.x; j < a.n_valid; j += kThreads) {
     const double v = L[j];
     if (v >= thr) {
       const int f = a.epts[j];
       const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
       if (!in_box(a.window, s, i1, i2)) continue;
+      if (a.window && a.redo_out) {
+        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+        for (int q = 0; q < 4; ++q) {
+          const int j1 = i1 + nb[q][0], j2 = i2 + nb[q][1];
+          if (grid_valid(j1, j2, a.n_e, a.half_r2) && !in_box(a.window, s, j1, j2)) atomicOr(&touch, 1);
+        }
+      }
       const double w = exp(v - best);
       const double x1 = (double)(i1 - ctr) * a.e_step, x2 = (double)(i2 - ctr) * a.e_step;
       sw += w;
@@ -187,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
     if (a.argmax) a.argmax[s] = f;
     if (a.n_above) a.n_above[s] = (int32_t)cnt;
     a.flags[s] = fl;
-    if (a.redo_out) a.redo_out[s] = inner_edge ? 1 : 0;
+    if (a.redo_out) a.redo_out[s] = (inner_edge || touch) ? 1 : 0;
   }
 }
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
+import sys
 
 import numpy as np
 
@@ -190,6 +191,10 @@ class Context:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the
+        # device memory to the process teardown
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -277,6 +282,10 @@ class Pass:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the
+        # device memory to the process teardown
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -294,6 +303,10 @@ class Facets:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the
+        # device memory to the process teardown
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -341,6 +354,10 @@ class Mlp:
             self.h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be gone: leave the
+        # device memory to the process teardown
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

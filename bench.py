@@ -74,8 +74,13 @@ def main():
     ap.add_argument("--only", action="store_true", help="time only the --precision form (for profiling)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the config-3 batched / surrogate block")
     ap.add_argument("--train-sources", type=int, default=200_000)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--nsigma", default="3,4", help="window half-widths (in predicted sigmas) to compare")
+    ap.add_argument("--populations", default="config1,config3",
+                    help="training source populations to compare (config-1 generator either way)")
+    ap.add_argument("--check-stride", type=int, default=4)
+    ap.add_argument("--full-frac", type=float, default=0.25,
+                    help="windows above this fraction of the grid are fitted on the whole grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -115,7 +120,9 @@ def main():
     }
     if not args.no_surrogate:
         res["batched_and_surrogate"] = run_surrogate(max(3, args.steps // 3), args.train_sources, args.epochs,
-                                                     [float(v) for v in args.nsigma.split(",")])
+                                                     [float(v) for v in args.nsigma.split(",")],
+                                                     args.populations.split(","), args.check_stride,
+                                                     args.full_frac)
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} sources")
         res["cpu_baseline"] = cpu_baseline(main_form["obs_host"], None, main_form["cat"], args.cpu_sample,
@@ -123,28 +130,29 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def run_surrogate(steps, n_train, epochs, nsigmas):
+def _evaluated_points(win, stride):
+    """Valid grid points inside each window plus the lattice points outside it."""
+    i = np.arange(81)
+    i1, i2 = np.meshgrid(i, i, indexing="ij")
+    valid = (i1 - 40) ** 2 + (i2 - 40) ** 2 < 2500
+    lat = valid & ((i1 - 40) % stride == 0) & ((i2 - 40) % stride == 0)
+    cv = np.pad(np.cumsum(np.cumsum(valid, 0), 1), ((1, 0), (1, 0)))
+    cl = np.pad(np.cumsum(np.cumsum(lat, 0), 1), ((1, 0), (1, 0)))
+    box = lambda c, w: c[w[:, 1] + 1, w[:, 3] + 1] - c[w[:, 0], w[:, 3] + 1] - c[w[:, 1] + 1, w[:, 2]] + c[w[:, 0], w[:, 2]]
+    return int(np.sum(box(cv, win)) + np.sum(int(lat.sum()) - box(cl, win)))
+
+
+def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, full_frac):
     """Config 3 (10,000 sources, 8 channels, mixed form): the captured batched
     pass, and the full-grid fit against the network-narrowed fit (network
-    trained here on facets simulated from config 1), the full grid judging
-    the narrowed result."""
+    trained here on facets simulated with the config-1 generator), the full
+    grid judging the narrowed result."""
     import torch
 
     from paper_2203_14071_amd import rlf, surrogate, synth
 
     stream = torch.cuda.current_stream()
     ctx = rlf.Context(0, stream.cuda_stream, rlf.params(precision=rlf.RLF_MIXED))
-    net = rlf.Mlp(ctx, 512)
-    net.set_state(surrogate.init_params())
-    t0 = time.perf_counter()
-    x, tg = surrogate.training_set(ctx, net, n_train, 20_000, log=log)
-    t_sim = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    hist = surrogate.train(ctx, net, x, tg, epochs, log=log)
-    t_train = time.perf_counter() - t0
-    del x, tg
-    torch.cuda.empty_cache()
-
     cfg = synth.CONFIGS[3]
     o = synth.observation(3)
     cat = synth.catalogue(cfg, synth.rng(3, synth.STREAM_CAT))
@@ -152,6 +160,7 @@ def run_surrogate(steps, n_train, epochs, nsigmas):
     dev = "cuda:0"
     t = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
     obs = rlf.Obs(t(o.u_m), t(o.v_m), t(o.w_m), o.freq_hz, t(nz, torch.complex64), t(o.weight, torch.float32))
+    del nz
     ctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
     catc = cat.with_shape(np.zeros(cat.n_src), np.zeros(cat.n_src))
     n = cat.n_src
@@ -179,29 +188,53 @@ def run_surrogate(steps, n_train, epochs, nsigmas):
     t_full = timed(lambda: ctx.fit_sources(f, full))
     a = {k: v.cpu().numpy() for k, v in full.items()}
     fit_rms = float(np.sqrt(np.nanmean((a["e1"] - cat.e1) ** 2 + (a["e2"] - cat.e2) ** 2) / 2))
-    win = surrogate.Windowed(ctx, net, n)
-    narrowed = []
-    for ns in nsigmas:
-        nar = outs()
-        t_nar = timed(lambda: win.fit(f, nar, nsigma=ns))
-        b = {k: v.cpu().numpy() for k, v in nar.items()}
-        ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
-        de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
-        w = win.win.cpu().numpy()
-        area = (w[:, 1] - w[:, 0] + 1) * (w[:, 3] - w[:, 2] + 1)
-        y = win.y.cpu().numpy()
-        pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
-        rms = float(np.sqrt(np.mean(de ** 2)))
-        fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
-        log(f"[bench] config 3, nsigma {ns}: narrowed fit {t_nar:.2f} ms (full {t_full:.2f} ms); "
-            f"RMS(de) {rms:.2e}; fallback {fb:.3f}; window {area.mean():.0f} points")
-        narrowed.append({"nsigma": ns, "fit_ms": round(t_nar, 3), "fit_sources_per_s": round(n / (t_nar * 1e-3), 1),
-                         "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
-                         "fit_speedup_vs_plain": round(t_full / t_nar, 3),
-                         "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
-                         "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
-                         "mean_window_points": round(float(area.mean()), 1),
-                         "network_rms_e_vs_true": round(pred_rms, 4)})
+    log(f"[bench] config 3: extract {t_ext:.2f} ms, full fit {t_full:.2f} ms")
+    narrowed, training = [], []
+    for pop in populations:
+        net = rlf.Mlp(ctx, 512)
+        net.set_state(surrogate.init_params())
+        t0 = time.perf_counter()
+        x, tg = surrogate.training_set(ctx, net, n_train, 20_000, log=log, population=pop)
+        t_sim = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hist = surrogate.train(ctx, net, x, tg, epochs, log=log)
+        t_train = time.perf_counter() - t0
+        del x, tg
+        torch.cuda.empty_cache()
+        training.append({"population": pop, "sources": n_train, "epochs": epochs, "simulate_s": round(t_sim, 2),
+                         "train_s": round(t_train, 2), "loss_per_epoch": [round(h, 4) for h in hist]})
+        win = surrogate.Windowed(ctx, net, n)
+        t_feat = timed(lambda: (net.features(f, win.x), net.forward(win.x, win.y)))
+        for ns in nsigmas:
+            nar = outs()
+            t_nar = timed(lambda: win.fit(f, nar, nsigma=ns, check_stride=check_stride, full_frac=full_frac))
+            b = {k: v.cpu().numpy() for k, v in nar.items()}
+            ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
+            de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
+            w = win.win.cpu().numpy()
+            area = (w[:, 1] - w[:, 0] + 1) * (w[:, 3] - w[:, 2] + 1)
+            refit = (b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0
+            evals = _evaluated_points(w, check_stride) + np.count_nonzero(refit) * 6333
+            y = win.y.cpu().numpy()
+            pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
+            rms = float(np.sqrt(np.mean(de ** 2)))
+            fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
+            log(f"[bench] config 3, {pop} network, nsigma {ns}: narrowed fit {t_nar:.2f} ms "
+                f"(full {t_full:.2f} ms); RMS(de) {rms:.2e}; fallback {fb:.3f}; window {area.mean():.0f} points")
+            narrowed.append({"training_population": pop, "nsigma": ns, "check_stride": check_stride,
+                             "fit_ms": round(t_nar, 3), "of_which_features_and_network_ms": round(t_feat, 3),
+                             "fit_sources_per_s": round(n / (t_nar * 1e-3), 1),
+                             "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
+                             "fit_speedup_vs_plain": round(t_full / t_nar, 3),
+                             "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                             "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
+                             "mean_window_points": round(float(area.mean()), 1),
+                             "full_grid_windows": int(np.count_nonzero(area == 81 * 81)),
+                             "grid_points_evaluated_vs_full": round(evals / (6333 * n), 4),
+                             "network_rms_e_vs_true": round(pred_rms, 4)})
+        net.free()
+        del win
+        torch.cuda.empty_cache()
 
     # the captured batched pass (residual + extraction + queue likelihood + estimate)
     out_p = outs()
@@ -211,7 +244,7 @@ def run_surrogate(steps, n_train, epochs, nsigmas):
     ps.free()
     cells = np.diff(f.copy()["offsets"])
     f.free()
-    log(f"[bench] config 3: extract {t_ext:.2f} ms, full fit {t_full:.2f} ms, captured pass {t_pass:.2f} ms")
+    log(f"[bench] config 3: captured pass {t_pass:.2f} ms")
     res = {
         "workload": f"{cfg.name}: {cfg.n_ant} antennas, {o.n_rows} rows x {o.n_chan} channels, "
                     f"{n} sources, mixed form",
@@ -222,12 +255,12 @@ def run_surrogate(steps, n_train, epochs, nsigmas):
         "plain": {"extract_ms": round(t_ext, 3), "fit_ms": round(t_full, 3),
                   "fit_sources_per_s": round(n / (t_full * 1e-3), 1),
                   "end_to_end_sources_per_s": round(n / ((t_ext + t_full) * 1e-3), 1),
-                  "rms_e_vs_true": round(fit_rms, 4)},
+                  "rms_e_vs_true": round(fit_rms, 4),
+                  "posterior_sd_quantiles": {q: round(float(np.nanquantile(np.maximum(a["s1"], a["s2"]), q)), 4)
+                                             for q in (0.1, 0.25, 0.5, 0.75, 0.9)}},
         "surrogate": narrowed,
-        "training": {"sources": n_train, "epochs": epochs, "simulate_s": round(t_sim, 2),
-                     "train_s": round(t_train, 2), "loss_per_epoch": [round(h, 4) for h in hist]},
+        "training": training,
     }
-    net.free()
     ctx.close()
     del obs
     torch.cuda.empty_cache()

@@ -212,10 +212,15 @@ typedef struct {
   int32_t mode;            /* 0 = full grid; 1 = windowed (window must be set)              */
   int32_t want_surface;    /* nonzero: write out->surface                                    */
   const int32_t *window;   /* device [n_src*4] inclusive (i1lo, i1hi, i2lo, i2hi) grid boxes */
-  int32_t fallback;        /* windowed mode: nonzero = refit on the full grid every source
-                              whose maximum, or any member of its thresholded set, lies on a
-                              window edge that is not the domain edge */
-  int32_t reserved;        /* must be 0 */
+  int32_t fallback;        /* windowed mode: nonzero = refit on the full grid (flag
+                              RLF_FLAG_FALLBACK) every source of a non-empty facet whose window
+                              holds no valid grid point, or where a member of the window's
+                              thresholded set has a grid neighbour (|e| < 1) outside the window */
+  int32_t check_stride;    /* windowed mode with fallback: 0 = off; S in [2, n_e-1] = also
+                              evaluate the valid points outside the window whose offsets from
+                              the grid centre are multiples of S on both axes, and refit when
+                              one of them reaches the window's thresholded set (a separate
+                              region of high likelihood).  Must be 0 otherwise. */
 } rlf_fit_opts;
 
 /* Fit outputs, device arrays [n_src] (surface [n_src*n_e*n_e]).  Any pointer
@@ -278,13 +283,15 @@ int rlf_pass_free(rlf_pass *pass);
  * An MLP maps a facet to (e1, e2, ln alpha) and their log-variances; its
  * predictions centre narrowed ellipticity windows for rlf_fit_sources
  * (mode 1 with fallback), the full-grid fit staying the judge.
- *   input   8192 values: the facet's cells with -32 <= ix, iy <= 31, Vbar / S
- *           (S the catalogue flux), Re at (iy+32)*64 + ix+32, Im at 4096 +
- *           the same index, 0 for empty cells; BF16 [n x 8192] row-major
+ *   input   8192 values: the facet's cells with -32 <= ix, iy <= 31,
+ *           Vbar / (S g) (S the catalogue flux at nu_ref, g the observation's
+ *           mean spectral factor of Eq. 1) clipped to [-4, 4], Re at (iy+32)*64 + ix+32, Im at
+ *           4096 + the same index, 0 for empty cells; BF16 [n x 8192] row-major
  *   layers  z_l = h_{l-1} W_l + b_l, h_l = GELU(z_l) = z Phi(z) (l = 1..3,
  *           width 512), y = h_3 W_4 + b_4 (6 outputs, FP32 [n x 6]:
  *           mu = y[0:3], s = y[3:6] log-variances)
- *   loss    mean over samples of sum_d (s_d + (t_d - mu_d)^2 exp(-s_d)) / 2
+ *   loss    mean over samples of sum_d (s'_d + (t_d - mu_d)^2 exp(-s'_d)) / 2,
+ *           s' = max(s, ln 1e-3) (no gradient to s below the floor)
  * Products are BF16 on MFMA with FP32 accumulation; FP32 master weights,
  * Adam (0.9, 0.999, 1e-8).  Parameters, FP32, in this order: W1 [8192 x 512],
  * b1 [512], W2 [512 x 512], b2, W3 [512 x 512], b3, W4 [512 x 6], b4 [6]
@@ -309,7 +316,9 @@ int rlf_mlp_set_state(rlf_mlp *net, const float *params, const float *adam_m, co
 int rlf_mlp_get_state(rlf_mlp *net, float *params, float *adam_m, float *adam_v, float *grad, int64_t *step);
 
 /* Network inputs of every source of the last extraction: device BF16
- * [n_src x 8192]. */
+ * [n_src x 8192], Vbar / (S g) with g the mean over the observation's
+ * channels of (nu_c / nu_ref)^beta (1 for one channel at nu_ref), each part
+ * clipped to [-4, 4]. */
 int rlf_mlp_features(rlf_ctx *ctx, const rlf_facets *facets, void *x);
 
 /* y = network(x) for `rows` inputs: x device BF16 [rows x 8192], y device
@@ -322,11 +331,14 @@ int rlf_mlp_forward(rlf_mlp *net, const void *x, int64_t rows, float *y);
 int rlf_mlp_train_step(rlf_mlp *net, const void *x, const float *target, int64_t rows, float lr, double *loss);
 
 /* Window boxes for rlf_fit_sources mode 1 from predictions y (device FP32
- * [rows x 6]): per axis, mu +- nsigma exp(s/2), widened to at least
- * +- min_half grid steps around the nearest grid point, snapped outward and
- * clamped to the grid; written as device int32 [rows x 4]
- * (i1lo, i1hi, i2lo, i2hi). */
-int rlf_mlp_windows(rlf_ctx *ctx, const float *y, int64_t rows, double nsigma, int32_t min_half, int32_t *window);
+ * [rows x 6]): per axis, mu +- nsigma exp(s'/2) (s' the floored
+ * log-variance), widened to at least +- min_half grid steps around the
+ * nearest grid point, snapped outward and clamped to the grid; a box
+ * covering more than full_frac (in [0, 1]) of the n_e x n_e grid becomes the
+ * whole grid (a broad prediction gains nothing from a window and would pay
+ * for a refit).  Written as device int32 [rows x 4] (i1lo, i1hi, i2lo, i2hi). */
+int rlf_mlp_windows(rlf_ctx *ctx, const float *y, int64_t rows, double nsigma, int32_t min_half, double full_frac,
+                    int32_t *window);
 
 #ifdef __cplusplus
 }

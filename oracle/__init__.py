@@ -33,4 +33,4 @@ from .extract import Facet, facet_theta, extract_facet, extract_facets
 from .likelihood import (alpha_knots, spline_quadrature_weights, log_normal_prior,
                          e_grid, loglike_alpha, marginal_surface, log_alpha_weights)
 from .estimate import Estimate, estimate, FLAG_BAD_VAR, FLAG_EMPTY, FLAG_EDGE, FLAG_FALLBACK
-from .fit import Params, fit_source, fit_sources
+from .fit import Params, fit_source, fit_sources, narrowed_fit, window_rejected

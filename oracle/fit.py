@@ -5,10 +5,11 @@ place of the simplex maximiser and the adaptive sampler.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
-from .estimate import FLAG_EMPTY, Estimate, estimate
+from .estimate import FLAG_EMPTY, FLAG_FALLBACK, Estimate, estimate
 from .likelihood import alpha_knots, e_grid, log_alpha_weights, marginal_surface
 
 
@@ -53,6 +54,56 @@ def fit_source(facet, flux_jy, p: Params = Params(), mu=None, window=None):
     surf[valid] = marginal_surface(facet, e1[valid], e2[valid], knots, logw)
     est = estimate(surf, e1, e2, valid, p.n_e, p.frac, p.bad_sigma, p.bad_sqrtdet)
     return surf, est
+
+
+def window_rejected(surface, window, check_stride=0, p: Params = Params()):
+    """The rule by which a narrowed fit distrusts its window (not in the
+    paper).  surface: flattened [n_e*n_e] ln L(e), read inside the window and,
+    with check_stride S > 0, at the lattice points outside it.  The window is
+    rejected when
+      * it holds no valid grid point (|e| < 1), or
+      * a member of its thresholded set {ln L >= ln Lmax_w + ln frac} (Lmax_w
+        the maximum inside the window) has one of its four grid neighbours
+        valid but outside the window (the set, or the maximum, may continue
+        beyond the window), or
+      * S > 0 and a valid point outside the window whose offsets (i1 - c,
+        i2 - c) from the grid centre are both multiples of S reaches that set
+        (a separate region of high likelihood)."""
+    i1, i2, _, _, valid = e_grid(p.n_e, p.e_step)
+    a, b, c, d = window
+    inside = (i1 >= a) & (i1 <= b) & (i2 >= c) & (i2 <= d)
+    win = valid & inside
+    if not np.any(win):
+        return True
+    thr = float(np.max(surface[win])) + math.log(p.frac)
+    member = (win & (surface >= thr)).reshape(p.n_e, p.n_e)
+    out = np.zeros((p.n_e + 2, p.n_e + 2), dtype=bool)          # valid and outside, padded by one
+    out[1:-1, 1:-1] = (valid & ~inside).reshape(p.n_e, p.n_e)
+    for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        if np.any(member & out[1 + di:p.n_e + 1 + di, 1 + dj:p.n_e + 1 + dj]):
+            return True
+    if check_stride > 0:
+        ctr = (p.n_e - 1) // 2
+        lat = valid & ~inside & ((i1 - ctr) % check_stride == 0) & ((i2 - ctr) % check_stride == 0)
+        if np.any(surface[lat] >= thr):
+            return True
+    return False
+
+
+def narrowed_fit(facet, flux_jy, window, check_stride=0, p: Params = Params(), mu=None):
+    """Fit on an ellipticity window; where window_rejected holds for a
+    non-empty facet, the full-grid fit replaces it, flagged FALLBACK.
+    Returns (surface, estimate, refitted)."""
+    surf, est = fit_source(facet, flux_jy, p, mu, window)
+    if facet.n_cells == 0:
+        return surf, est, False
+    full, full_est = fit_source(facet, flux_jy, p, mu)
+    seen = full.copy()                          # the window's own values inside it
+    inw = np.isfinite(surf)
+    seen[inw] = surf[inw]
+    if not window_rejected(seen, window, check_stride, p):
+        return surf, est, False
+    return full, dataclasses.replace(full_est, flags=full_est.flags | FLAG_FALLBACK), True
 
 
 def fit_sources(facets, flux_jy, p: Params = Params(), mu=None):

@@ -3,12 +3,18 @@
 Not part of the paper: a small MLP that predicts (e1, e2, ln alpha) and
 their log-variances from a facet, used to centre a narrowed ellipticity grid.
 
-  input   x: the facet's cells with -32 <= ix, iy <= 31, Vbar / S (S the
-          catalogue flux): Re at (iy+32)*64 + ix+32, Im at 4096 + same, 0 for
-          empty cells  -> 8192 values, rounded to BF16
+  input   x: the facet's cells with -32 <= ix, iy <= 31, Vbar / (S g) (S the
+          catalogue flux at the reference frequency, g the mean over the
+          observation's channels of the spectral factor (nu_c / nu_ref)^beta of
+          Eq. 1), clipped to [-X_CLIP, X_CLIP] (the noise of faint sources
+          would otherwise reach hundreds): Re at (iy+32)*64 + ix+32, Im at
+          4096 + same, 0 for empty cells  -> 8192 values, rounded to BF16
   layers  z_l = h_{l-1} W_l + b_l,  h_l = GELU(z_l) = z Phi(z)  (l = 1..3, width 512)
           y = h_3 W_4 + b_4  (6 outputs: mu = y[0:3], s = y[3:6] log-variances)
-  loss    mean over samples of sum_d (s_d + (t_d - mu_d)^2 exp(-s_d)) / 2
+  loss    mean over samples of sum_d (s'_d + (t_d - mu_d)^2 exp(-s'_d)) / 2,
+          s' = max(s, S_MIN): the predicted variance is floored at 1e-3 (a
+          sample whose prediction sits below the floor passes no gradient to
+          its s), which bounds the loss of confident misses
 
 BF16 rounding (round to nearest even, from the FP32 value) is applied where
 the kernels round: inputs, weights and activations before each product, and
@@ -25,6 +31,8 @@ import numpy as np
 from scipy.special import erf
 
 N_IN, N_HID, N_OUT, N_TGT = 8192, 512, 6, 3
+S_MIN = math.log(1e-3)
+X_CLIP = 4.0
 SHAPES = [("W1", (N_IN, N_HID)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_HID, N_HID)), ("b3", (N_HID,)), ("W4", (N_HID, N_OUT)), ("b4", (N_OUT,))]
 
@@ -63,13 +71,19 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def features(ix, iy, vbar, flux):
-    """Network input of one facet (cells ix, iy, complex Vbar), unrounded."""
+def spectral_norm(freq_hz, ref_freq_hz=1.4e9, beta=-0.7):
+    """g: mean over channels of the spectral factor (nu_c / nu_ref)^beta."""
+    return float(np.mean((np.asarray(freq_hz, dtype=np.float64) / ref_freq_hz) ** beta))
+
+
+def features(ix, iy, vbar, norm):
+    """Network input of one facet (cells ix, iy, complex Vbar) divided by
+    norm = S g and clipped, unrounded."""
     x = np.zeros(N_IN)
     keep = (ix >= -32) & (ix <= 31) & (iy >= -32) & (iy <= 31)
     pos = (iy[keep] + 32) * 64 + (ix[keep] + 32)
-    x[pos] = vbar.real[keep] / flux
-    x[4096 + pos] = vbar.imag[keep] / flux
+    x[pos] = np.clip(vbar.real[keep] / norm, -X_CLIP, X_CLIP)
+    x[4096 + pos] = np.clip(vbar.imag[keep] / norm, -X_CLIP, X_CLIP)
     return x
 
 
@@ -88,7 +102,7 @@ def forward(x, p, round_bf16=True):
 
 
 def loss(y, t):
-    mu, s = y[:, :N_TGT], y[:, N_TGT:]
+    mu, s = y[:, :N_TGT], np.maximum(y[:, N_TGT:], S_MIN)
     return float(np.mean(np.sum(0.5 * (s + (t - mu) ** 2 * np.exp(-s)), axis=1)))
 
 
@@ -96,9 +110,11 @@ def backward(p, cache, t, round_bf16=True):
     r = bf16 if round_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     y = cache["y"]
     n = y.shape[0]
-    mu, s = y[:, :N_TGT], y[:, N_TGT:]
+    mu, s_raw = y[:, :N_TGT], y[:, N_TGT:]
+    s = np.maximum(s_raw, S_MIN)
     d = t - mu
-    dy = np.concatenate([-d * np.exp(-s), 0.5 * (1.0 - d * d * np.exp(-s))], axis=1) / n
+    ds = np.where(s_raw < S_MIN, 0.0, 0.5 * (1.0 - d * d * np.exp(-s)))
+    dy = np.concatenate([-d * np.exp(-s), ds], axis=1) / n
     g = {"b4": dy.sum(0)}
     dyr = r(dy)
     g["W4"] = cache["h3"].T @ dyr
@@ -126,16 +142,18 @@ def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return pn, mn, vn
 
 
-def windows(y, nsigma=3.0, n_e=81, step=0.02, min_half=3):
+def windows(y, nsigma=3.0, n_e=81, step=0.02, min_half=3, full_frac=1.0):
     """Inclusive e-grid boxes centred on the predicted (e1, e2): +-nsigma
-    predicted standard deviations, widened to at least +-min_half steps,
-    snapped outward to the grid, clamped to [0, n_e-1]."""
+    predicted standard deviations (from the floored log-variance), widened to
+    at least +-min_half steps, snapped outward to the grid, clamped to
+    [0, n_e-1]; a box holding more than full_frac of the n_e^2 grid points
+    becomes the whole grid."""
     c = (n_e - 1) // 2
     out = np.zeros((y.shape[0], 4), dtype=np.int64)
     for i in range(y.shape[0]):
         for d in (0, 1):
             mu = y[i, d]
-            sd = math.exp(0.5 * y[i, 3 + d])
+            sd = math.exp(0.5 * max(y[i, 3 + d], S_MIN))
             lo = math.floor((mu - nsigma * sd) / step + c)
             hi = math.ceil((mu + nsigma * sd) / step + c)
             mid = int(round(mu / step + c))
@@ -143,4 +161,6 @@ def windows(y, nsigma=3.0, n_e=81, step=0.02, min_half=3):
             hi = max(hi, mid + min_half)
             out[i, 2 * d] = min(max(lo, 0), n_e - 1)
             out[i, 2 * d + 1] = min(max(hi, 0), n_e - 1)
+        if (out[i, 1] - out[i, 0] + 1) * (out[i, 3] - out[i, 2] + 1) > full_frac * n_e * n_e:
+            out[i] = (0, n_e - 1, 0, n_e - 1)
     return out

@@ -121,7 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
 
   // pass 2: weight, first moments, count over the thresholded set; with a
   // window, also whether any member has a grid neighbour outside the window
-  // (the set may continue beyond it: the narrowed result is not trusted)
+  // (the set may continue beyond it: the narrowed result is not trusted) or
+  // an evaluated lattice point outside the window reaches the set
   const double thr = best + a.log_frac;
   double sw = 0.0, s1 = 0.0, s2 = 0.0, cnt = 0.0;
   if (threadIdx.x == 0) touch = 0;
@@ -131,7 +132,13 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
     if (v >= thr) {
       const int f = a.epts[j];
       const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
-      if (!in_box(a.window, s, i1, i2)) continue;
+      if (!in_box(a.window, s, i1, i2)) {
+        // a lattice point outside the window reaching the set: refit
+        if (a.redo_out && a.check_stride > 0 && (i1 - ctr) % a.check_stride == 0 &&
+            (i2 - ctr) % a.check_stride == 0)
+          atomicOr(&touch, 1);
+        continue;
+      }
       if (a.window && a.redo_out) {
         const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
         for (int q = 0; q < 4; ++q) {

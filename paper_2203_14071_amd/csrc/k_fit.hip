@@ -130,21 +130,51 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
   eval_point<R, kExact, kMixed>(a, num_r, s, j);
 }
 
-// Windowed launch: blockIdx.y = source; threads enumerate the source's
-// inclusive box (i1lo, i1hi, i2lo, i2hi) row-major and evaluate its valid
-// points.  Points outside the box are not evaluated (the estimator skips them).
+// Windowed launch: blockIdx.y = source, one thread per position of the
+// source's inclusive box (i1lo, i1hi, i2lo, i2hi) in row-major order, then,
+// with a check stride S, per lattice point c + S q (both axes, |q| <= c / S)
+// outside the box; invalid points (|e| >= 1) are skipped.  No other point is
+// evaluated (the estimator reads no other).  Blocks past a source's positions
+// leave at once, so the grid is sized for the largest possible box.
 template <int R, bool kExact, bool kMixed>
 __global__ __launch_bounds__(256) void k_fit_window(FitArgs a, int num_r) {
   const int s = blockIdx.y;
-  const int4 b = reinterpret_cast<const int4 *>(a.window)[s];
-  const int w2 = b.w - b.z + 1;
-  const int area = (b.y - b.x + 1) * w2;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < area; t += gridDim.x * blockDim.x) {
-    const int i1 = b.x + t / w2, i2 = b.z + t % w2;
-    if (i1 < 0 || i2 < 0 || i1 >= a.n_e || i2 >= a.n_e) continue;
-    const int j = a.valid_index[i1 * a.n_e + i2];
-    if (j >= 0) eval_point<R, kExact, kMixed>(a, num_r, s, j);
+  int4 b = reinterpret_cast<const int4 *>(a.window)[s];
+  b.x = max(b.x, 0);                          // the box's part on the grid: at most n_e^2 positions
+  b.y = min(b.y, a.n_e - 1);
+  b.z = max(b.z, 0);
+  b.w = min(b.w, a.n_e - 1);
+  const int w2 = b.w >= b.z ? b.w - b.z + 1 : 1;
+  const int area = (b.y >= b.x && b.w >= b.z) ? (b.y - b.x + 1) * w2 : 0;
+  const int ctr = (a.n_e - 1) / 2;
+  const int h = a.check_stride > 0 ? ctr / a.check_stride : 0;
+  const int nl = a.check_stride > 0 ? 2 * h + 1 : 0;
+  // a box with at least as many positions as the grid has valid points is
+  // walked over the valid points instead (no idle lanes on |e| >= 1)
+  const bool by_valid = area >= a.n_valid;
+  const int span = by_valid ? a.n_valid : area;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= span + nl * nl) return;
+  int i1, i2;
+  if (by_valid && t < span) {
+    const int f = a.epts[t];
+    i1 = f / a.n_e;
+    i2 = f - i1 * a.n_e;
+    if (i1 >= b.x && i1 <= b.y && i2 >= b.z && i2 <= b.w) eval_point<R, kExact, kMixed>(a, num_r, s, t);
+    return;
   }
+  if (t < span) {
+    i1 = b.x + t / w2;
+    i2 = b.z + t % w2;
+  } else {
+    const int u = t - span;
+    i1 = ctr + a.check_stride * (u / nl - h);
+    i2 = ctr + a.check_stride * (u % nl - h);
+    if (i1 >= b.x && i1 <= b.y && i2 >= b.z && i2 <= b.w) return;   // evaluated with the box
+  }
+  if (i1 < 0 || i2 < 0 || i1 >= a.n_e || i2 >= a.n_e) return;
+  const int j = a.valid_index[i1 * a.n_e + i2];
+  if (j >= 0) eval_point<R, kExact, kMixed>(a, num_r, s, j);
 }
 
 // Persistent work queue: a grid sized to the resident capacity; each wave
@@ -196,7 +226,9 @@ __global__ void k_reset_counter(uint32_t *c) {
 template <bool kMixed>
 hipError_t launch(const FitArgs &a, hipStream_t st) {
   if (a.window) {
-    RLF_FIT_DISPATCH(k_fit_window, dim3(a.window_blocks, a.n_src), a);
+    const int h = a.check_stride > 0 ? ((a.n_e - 1) / 2) / a.check_stride : 0;
+    const int positions = a.n_e * a.n_e + (a.check_stride > 0 ? (2 * h + 1) * (2 * h + 1) : 0);
+    RLF_FIT_DISPATCH(k_fit_window, dim3((positions + 255) / 256, a.n_src), a);
   } else {
     RLF_FIT_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
   }

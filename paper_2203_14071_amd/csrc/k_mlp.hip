@@ -28,6 +28,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBM = 128, kBN = 128, kBK = 32, kPad = 8, kLd = kBK + kPad;
+constexpr float kLogVarMin = -6.9077552789821368f;   // ln(1e-3)
+constexpr double kFeatureClip = 4.0;
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return __float2bfloat16(x); }
 
@@ -143,18 +145,21 @@ __global__ __launch_bounds__(256) void k_bias_act(const float *c, const float *b
 }
 
 // Gaussian negative log-likelihood head: y [n x 6] -> loss (added to *loss),
-// dY = dL/dy (FP32 for the bias, BF16 for the products).
+// dY = dL/dy (FP32 for the bias, BF16 for the products).  The log-variance is
+// floored at kLogVarMin (variance 1e-3); below the floor it gets no gradient.
 __global__ __launch_bounds__(256) void k_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb,
                                               double *loss) {
   __shared__ double sh[4];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     for (int d = 0; d < 3; ++d) {
-      const float mu = y[i * 6 + d], s = y[i * 6 + 3 + d];
+      const float mu = y[i * 6 + d], s_raw = y[i * 6 + 3 + d];
+      const float s = fmaxf(s_raw, kLogVarMin);
       const float e = t[i * 3 + d] - mu;
       const float ie = expf(-s);
       acc += 0.5 * ((double)s + (double)e * e * ie);
-      const float gm = -e * ie / (float)n, gs = 0.5f * (1.0f - e * e * ie) / (float)n;
+      const float gm = -e * ie / (float)n;
+      const float gs = s_raw < kLogVarMin ? 0.0f : 0.5f * (1.0f - e * e * ie) / (float)n;
       dy[i * 6 + d] = gm;
       dy[i * 6 + 3 + d] = gs;
       dyb[i * 6 + d] = to_bf16(gm);
@@ -209,38 +214,46 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *x, __bf16 *y, int6
     y[i] = to_bf16(x[i]);
 }
 
-// Network input: facet cells inside -32..31 on both axes, Vbar / S.
+// Network input: facet cells inside -32..31 on both axes, Vbar / (S g), g the
+// observation's mean spectral factor, clipped to +-kFeatureClip.
 __global__ __launch_bounds__(256) void k_features(FeatureArgs a) {
   const int s = blockIdx.x;
   __bf16 *x = a.x + (int64_t)s * 8192;
   for (int i = threadIdx.x; i < 8192; i += blockDim.x) x[i] = to_bf16(0.0f);
   __syncthreads();
-  const double inv = 1.0 / a.src[s].flux;
+  const double inv = 1.0 / (a.src[s].flux * a.spec_norm);
   for (int64_t c = a.offsets[s] + threadIdx.x; c < a.offsets[s + 1]; c += blockDim.x) {
     const int ix = a.ix[c], iy = a.iy[c];
     if (ix < -32 || ix > 31 || iy < -32 || iy > 31) continue;
     const int pos = (iy + 32) * 64 + (ix + 32);
-    x[pos] = to_bf16((float)(a.vre[c] * inv));
-    x[4096 + pos] = to_bf16((float)(a.vim[c] * inv));
+    x[pos] = to_bf16((float)fmin(fmax(a.vre[c] * inv, -kFeatureClip), kFeatureClip));
+    x[4096 + pos] = to_bf16((float)fmin(fmax(a.vim[c] * inv, -kFeatureClip), kFeatureClip));
   }
 }
 
-// Window boxes from the predictions (decided in FP64 from the FP32 outputs).
+// Window boxes from the predictions (decided in FP64 from the FP32 outputs);
+// a box covering more than full_frac of the grid becomes the whole grid.
 __global__ __launch_bounds__(256) void k_windows(const float *y, int64_t n, double nsigma, int n_e, double step,
-                                                 int min_half, int32_t *win) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+                                                 int min_half, double full_frac, int32_t *win) {
   const int c = (n_e - 1) / 2;
-  for (int d = 0; d < 2; ++d) {
-    const double mu = (double)y[i * 6 + d];
-    const double sd = exp(0.5 * (double)y[i * 6 + 3 + d]);
-    int lo = (int)floor((mu - nsigma * sd) / step + c);
-    int hi = (int)ceil((mu + nsigma * sd) / step + c);
-    const int mid = (int)rint(mu / step + c);
-    lo = min(lo, mid - min_half);
-    hi = max(hi, mid + min_half);
-    win[i * 4 + 2 * d] = min(max(lo, 0), n_e - 1);
-    win[i * 4 + 2 * d + 1] = min(max(hi, 0), n_e - 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int box[4];
+    for (int d = 0; d < 2; ++d) {
+      const double mu = (double)y[i * 6 + d];
+      const double sd = exp(0.5 * fmax((double)y[i * 6 + 3 + d], (double)kLogVarMin));
+      int lo = (int)floor((mu - nsigma * sd) / step + c);
+      int hi = (int)ceil((mu + nsigma * sd) / step + c);
+      const int mid = (int)rint(mu / step + c);
+      lo = min(lo, mid - min_half);
+      hi = max(hi, mid + min_half);
+      box[2 * d] = min(max(lo, 0), n_e - 1);
+      box[2 * d + 1] = min(max(hi, 0), n_e - 1);
+    }
+    if ((double)(box[1] - box[0] + 1) * (double)(box[3] - box[2] + 1) > full_frac * (double)n_e * (double)n_e) {
+      box[0] = box[2] = 0;
+      box[1] = box[3] = n_e - 1;
+    }
+    for (int q = 0; q < 4; ++q) win[i * 4 + q] = box[q];
   }
 }
 
@@ -301,9 +314,10 @@ hipError_t launch_features(const FeatureArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half, int32_t *win,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_windows, dim3(grid_for(n)), dim3(256), 0, st, y, n, nsigma, n_e, step, min_half, win);
+hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half,
+                          double full_frac, int32_t *win, hipStream_t st) {
+  hipLaunchKernelGGL(k_windows, dim3(grid_for(n)), dim3(256), 0, st, y, n, nsigma, n_e, step, min_half, full_frac,
+                     win);
   return hipGetLastError();
 }
 

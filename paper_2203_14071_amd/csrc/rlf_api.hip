@@ -528,6 +528,11 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
   f->ctx = c;
   f->n_src = cat->n_src;
   f->mixed = c->p.precision == RLF_MIXED;
+  {
+    double g = 0.0;
+    for (int32_t k = 0; k < obs->n_chan; ++k) g += std::pow(obs->freq_hz_host[k] / c->p.ref_freq_hz, c->p.beta);
+    f->spec_norm = g / obs->n_chan;
+  }
   f->alpha.assign(cat->alpha_arcsec, cat->alpha_arcsec + cat->n_src);
   f->theta.resize((size_t)cat->n_src);
   f->geom.resize((size_t)cat->n_src);
@@ -741,7 +746,8 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   if (!out || !out->flags) return fail(c, RLF_EINVAL, "out/out.flags is NULL");
   rlf_fit_opts o{};
   if (opts) o = *opts;
-  if (o.reserved != 0) return fail(c, RLF_EINVAL, "opts.reserved must be 0");
+  if (o.check_stride != 0 && (o.mode != 1 || !o.fallback || o.check_stride < 2 || o.check_stride >= c->p.n_e))
+    return fail(c, RLF_EINVAL, "opts.check_stride: 0, or 2..n_e-1 in windowed mode with fallback");
   if (o.mode != 0 && o.mode != 1) return fail(c, RLF_EINVAL, "opts.mode");
   if (o.mode == 1 && !o.window) return fail(c, RLF_EINVAL, "windowed mode needs opts.window");
   if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
@@ -770,7 +776,7 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   fa.fit64 = f->cells.fit64;
   fa.fit32 = f->cells.fit32;
   fa.window = windowed ? o.window : nullptr;
-  fa.window_blocks = 4;
+  fa.check_stride = (windowed && o.fallback) ? o.check_stride : 0;
   fa.redo = nullptr;
   fa.lsurf = f->d_lsurf;
   EstimateArgs ea{};
@@ -788,6 +794,7 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   ea.window = fa.window;
   ea.redo = nullptr;
   ea.redo_out = (windowed && o.fallback) ? f->d_redo : nullptr;
+  ea.check_stride = fa.check_stride;
   ea.e1 = out.e1;
   ea.e2 = out.e2;
   ea.s1 = out.s1;
@@ -808,8 +815,10 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   if (e != hipSuccess) return hip_fail(c, e, "estimate kernel launch");
   if (windowed && o.fallback) {
     fa.window = nullptr;
+    fa.check_stride = 0;
     fa.redo = f->d_redo;
     ea.window = nullptr;
+    ea.check_stride = 0;
     ea.redo = f->d_redo;
     ea.redo_out = nullptr;
     e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);

@@ -144,7 +144,7 @@ struct FitArgs {
   const double4 *fit64;
   const float4 *fit32;
   const int32_t *window;     // [n_src*4] inclusive grid boxes, or null (full grid)
-  int32_t window_blocks;     // windowed launch: blocks per source
+  int32_t check_stride;      // windowed launch: also the lattice points (multiples of it from the centre) outside the box
   const int32_t *valid_index; // [n_e*n_e] flat grid index -> valid-point index, -1 if |e| >= 1
   const int32_t *redo;       // fallback pass: [n_src] nonzero = evaluate; null = all
   double *lsurf;             // [n_src*n_valid] ln L(e) of the evaluated points
@@ -173,7 +173,8 @@ struct EstimateArgs {
   const double *lsurf;
   const int32_t *window;     // null = full grid
   const int32_t *redo;       // fallback pass: only these sources; null = all
-  int32_t *redo_out;         // windowed pass with fallback: set where the maximum is on an inner window edge
+  int32_t *redo_out;         // windowed pass with fallback: set where the window is not trusted
+  int32_t check_stride;      // lattice check outside the window (0 = off)
   double *e1, *e2, *s1, *s2, *c12, *lmax;
   int32_t *argmax, *n_above;
   uint32_t *flags;
@@ -200,6 +201,7 @@ struct FeatureArgs {
   const int32_t *ix, *iy;
   const double *vre, *vim;
   const SrcModel *src;
+  double spec_norm;          // mean over channels of (nu_c / nu_ref)^beta
   __bf16 *x;                 // [n_src * 8192]
 };
 
@@ -232,7 +234,7 @@ hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v,
                        hipStream_t st);
 hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);
 hipError_t launch_features(const FeatureArgs &a, hipStream_t st);
-hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half, int32_t *win,
-                          hipStream_t st);
+hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half,
+                          double full_frac, int32_t *win, hipStream_t st);
 
 }  // namespace rlf

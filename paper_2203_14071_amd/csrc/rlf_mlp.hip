@@ -216,6 +216,7 @@ int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {
   a.vre = f->cells.vre;
   a.vim = f->cells.vim;
   a.src = f->d_src;
+  a.spec_norm = f->spec_norm;
   a.x = reinterpret_cast<__bf16 *>(x);
   HIPCHK(c, launch_features(a, c->stream));
   return RLF_OK;
@@ -264,12 +265,13 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   return RLF_OK;
 }
 
-int rlf_mlp_windows(rlf_ctx *c, const float *y, int64_t rows, double nsigma, int32_t min_half, int32_t *window) {
+int rlf_mlp_windows(rlf_ctx *c, const float *y, int64_t rows, double nsigma, int32_t min_half, double full_frac,
+                    int32_t *window) {
   if (!c) return RLF_EINVAL;
-  if (!y || !window || rows < 1 || !(nsigma > 0) || min_half < 0)
+  if (!y || !window || rows < 1 || !(nsigma > 0) || min_half < 0 || !(full_frac >= 0.0 && full_frac <= 1.0))
     return fail(c, RLF_EINVAL, "rlf_mlp_windows: arguments");
   HIPCHK(c, hipSetDevice(c->device));
-  HIPCHK(c, launch_windows(y, rows, nsigma, c->p.n_e, c->p.e_step, min_half, window, c->stream));
+  HIPCHK(c, launch_windows(y, rows, nsigma, c->p.n_e, c->p.e_step, min_half, full_frac, window, c->stream));
   return RLF_OK;
 }
 

@@ -45,6 +45,7 @@ struct rlf_facets {
   int64_t n_src = 0;
   int64_t dense_total = 0;
   int mixed = 0;
+  double spec_norm = 1.0;                    // mean spectral factor over the channels
   std::vector<double> alpha;                 // catalogue sizes at creation
   std::vector<double> theta;
   std::vector<double> model_key;             // shapes of the uploaded model table

@@ -191,7 +191,8 @@ int rlf_pass_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
     return fail(c, RLF_EINVAL, "rlf_pass_create: NULL argument or facets from another context");
   rlf_fit_opts o{};
   if (opts) o = *opts;
-  if (o.reserved != 0 || (o.mode != 0 && o.mode != 1) || (o.mode == 1 && !o.window))
+  if ((o.mode != 0 && o.mode != 1) || (o.mode == 1 && !o.window) ||
+      (o.check_stride != 0 && (o.mode != 1 || !o.fallback || o.check_stride < 2 || o.check_stride >= c->p.n_e)))
     return fail(c, RLF_EINVAL, "rlf_pass_create: fit options");
   if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
   HIPCHK(c, hipSetDevice(c->device));

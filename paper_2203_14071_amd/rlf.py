@@ -50,7 +50,7 @@ class rlf_catalog(ctypes.Structure):
 
 class rlf_fit_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("want_surface", ctypes.c_int32), ("window", _c_vp),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("check_stride", ctypes.c_int32)]
 
 
 class rlf_fit_out(ctypes.Structure):
@@ -91,7 +91,8 @@ _SIGNATURES = {
     "rlf_mlp_features": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
     "rlf_mlp_forward": ([_c_vp, _c_vp, ctypes.c_int64, _c_vp], ctypes.c_int),
     "rlf_mlp_train_step": ([_c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_float, _c_vp], ctypes.c_int),
-    "rlf_mlp_windows": ([_c_vp, _c_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _c_vp], ctypes.c_int),
+    "rlf_mlp_windows": ([_c_vp, _c_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _c_vp],
+                        ctypes.c_int),
 }
 
 _lib = None
@@ -231,15 +232,16 @@ class Context:
         return self._check(lib().rlf_extract_facets(self.h, ctypes.byref(o), ctypes.byref(c), _ptr(residual),
                                                      facets.h))
 
-    def fit_sources(self, facets: "Facets", out: dict, mode=0, window=None, want_surface=False, fallback=False):
+    def fit_sources(self, facets: "Facets", out: dict, mode=0, window=None, want_surface=False, fallback=False,
+                    check_stride=0):
         """out: dict of torch device tensors e1, e2, s1, s2, c12, lmax (f64), argmax, n_above (i32),
         flags (i32 viewed as u32), surface (f64) -- any may be absent except flags."""
-        o, r = _fit_structs(out, mode, window, want_surface, fallback)
+        o, r = _fit_structs(out, mode, window, want_surface, fallback, check_stride)
         return self._check(lib().rlf_fit_sources(self.h, facets.h, ctypes.byref(o), ctypes.byref(r)))
 
     def pass_create(self, obs: Obs, cat, facets: "Facets", out: dict, tune_path=None, mode=0, window=None,
-                    want_surface=False, fallback=False, prior_mu=None) -> "Pass":
-        o, r = _fit_structs(out, mode, window, want_surface, fallback)
+                    want_surface=False, fallback=False, prior_mu=None, check_stride=0) -> "Pass":
+        o, r = _fit_structs(out, mode, window, want_surface, fallback, check_stride)
         ob = obs.c()
         c, keep = catalog(cat, prior_mu)
         h = _c_vp()
@@ -249,13 +251,13 @@ class Context:
         return Pass(self, h)
 
 
-def _fit_structs(out, mode, window, want_surface, fallback):
+def _fit_structs(out, mode, window, want_surface, fallback, check_stride=0):
     o = rlf_fit_opts()
     o.mode = int(mode)
     o.want_surface = 1 if want_surface else 0
     o.window = _ptr(window)
     o.fallback = 1 if fallback else 0
-    o.reserved = 0
+    o.check_stride = int(check_stride)
     r = rlf_fit_out()
     for k in ("e1", "e2", "s1", "s2", "c12", "lmax", "argmax", "n_above", "flags", "surface"):
         setattr(r, k, _ptr(out.get(k)))
@@ -388,9 +390,9 @@ class Mlp:
         return self.ctx._check(lib().rlf_mlp_train_step(self.h, _ptr(x), _ptr(target), int(x.shape[0]),
                                                         float(lr), _ptr(loss)))
 
-    def windows(self, y, window, nsigma=3.0, min_half=3):
+    def windows(self, y, window, nsigma=3.0, min_half=3, full_frac=1.0):
         return self.ctx._check(lib().rlf_mlp_windows(self.ctx.h, _ptr(y), int(y.shape[0]), float(nsigma),
-                                                     int(min_half), _ptr(window)))
+                                                     int(min_half), float(full_frac), _ptr(window)))
 
 
 def alpha_from_flux(flux_jy, add=-0.93, esp=0.33):

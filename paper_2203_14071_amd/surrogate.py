@@ -4,16 +4,20 @@ itself, train the network, and fit with narrowed ellipticity windows.
 Everything numeric runs in librlf.so (rlf_extract_facets, rlf_mlp_*,
 rlf_fit_sources); this module only arranges the calls and the buffers.
 
-Training facets: sources drawn from the SKA-MID-like field's distributions
-(config 1) at random positions, each isolated (the residual handed to the
-extraction is pure noise, so every facet holds its own exact model plus
-noise: the "single source" case of Sec. 4.2), a fresh noise realisation per
-batch of sources.  Targets are (e1, e2, ln alpha) of the drawn sources.
+Training facets come from the SKA-MID-like field generator (config 1: its
+array, 8 h track, one channel at 1.4 GHz and noise level), each source
+isolated (the residual handed to the extraction is pure noise, so every
+facet holds its own exact model plus noise: the "single source" case of
+Sec. 4.2), a fresh noise realisation per batch of sources.  The source
+population is config 1's (50-200 uJy, log-normal sizes) or, with
+population="config3", that of the 10,000-source field (10-1000 uJy, sizes
+from the size-flux relation), so that the network sees the signal-to-noise
+range it is used on.  Targets are (e1, e2, ln alpha) of the drawn sources.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
-import time
 
 import numpy as np
 
@@ -40,12 +44,24 @@ def init_params(seed_stream=synth.STREAM_INIT, out_scale=1e-3):
     return np.concatenate(parts)
 
 
+def training_population(population="config1"):
+    """The config-1 generator with the source population of `population`."""
+    cfg = synth.CONFIGS[1]
+    if population == "config1":
+        return cfg
+    if population == "config3":
+        c3 = synth.CONFIGS[3]
+        return dataclasses.replace(cfg, flux_min_ujy=c3.flux_min_ujy, flux_max_ujy=c3.flux_max_ujy,
+                                   flux_slope=c3.flux_slope, size_law=c3.size_law)
+    raise ValueError(population)
+
+
 def training_set(ctx: rlf.Context, net: rlf.Mlp, n_total=200_000, batch_src=20_000, device="cuda:0",
-                 log=None):
+                 log=None, population="config1"):
     """Simulate n_total training facets on the config-1 coverage; returns
     (x BF16 [n x 8192], targets FP32 [n x 3]) as device tensors."""
     import torch
-    cfg = synth.CONFIGS[1]
+    cfg = training_population(population)
     o = synth.observation(1)
     g = synth.rng(1, synth.STREAM_TRAIN)
     mixed = ctx.p.precision == rlf.RLF_MIXED
@@ -73,7 +89,7 @@ def training_set(ctx: rlf.Context, net: rlf.Mlp, n_total=200_000, batch_src=20_0
     return x, tg
 
 
-def train(ctx: rlf.Context, net: rlf.Mlp, x, tg, epochs=8, batch=512, lr=3e-4, log=None):
+def train(ctx: rlf.Context, net: rlf.Mlp, x, tg, epochs=8, batch=512, lr=1e-4, log=None):
     """Adam over contiguous batches (the sources are drawn i.i.d.); the
     learning rate drops to lr/4 for the last quarter of the steps.  Returns
     the per-epoch mean losses."""
@@ -111,10 +127,11 @@ class Windowed:
         self.y = torch.empty((n_src, 6), dtype=torch.float32, device=device)
         self.win = torch.empty((n_src, 4), dtype=torch.int32, device=device)
 
-    def fit(self, facets: rlf.Facets, out: dict, nsigma=3.0, min_half=3):
+    def fit(self, facets: rlf.Facets, out: dict, nsigma=3.0, min_half=3, check_stride=4, full_frac=0.25):
         """Enqueue features -> network -> windows -> windowed fit with the
-        full-grid fallback (no synchronisation)."""
+        full-grid fallback and its lattice check (no synchronisation).
+        Windows above full_frac of the grid are fitted on the whole grid."""
         self.net.features(facets, self.x)
         self.net.forward(self.x, self.y)
-        self.net.windows(self.y, self.win, nsigma, min_half)
-        self.ctx.fit_sources(facets, out, mode=1, window=self.win, fallback=True)
+        self.net.windows(self.y, self.win, nsigma, min_half, full_frac)
+        self.ctx.fit_sources(facets, out, mode=1, window=self.win, fallback=True, check_stride=check_stride)

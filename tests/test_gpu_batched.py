@@ -16,11 +16,13 @@ pytestmark = pytest.mark.gpu
 OUT_KEYS = ("e1", "e2", "s1", "s2", "c12", "lmax", "argmax", "n_above", "flags")
 
 
-def _field(n_src=120, n_ant=24, n_time=40, seed=31, freq=(1.0e9, 1.1e9)):
+def _field(n_src=120, n_ant=24, n_time=40, seed=31, freq=(1.0e9, 1.1e9), noise_scale=1.0):
     """Config 3 distributions (10-1000 uJy, Eq. 4 sizes: facets of widely
-    different sizes) on a reduced array with two channels."""
+    different sizes) on a reduced array with two channels; noise_scale
+    scales the noise level (and the weights with it)."""
     import dataclasses
-    cfg = dataclasses.replace(synth.small_config(3, n_ant=n_ant, n_time=n_time, n_src=n_src), freq_hz=freq)
+    cfg = synth.small_config(3, n_ant=n_ant, n_time=n_time, n_src=n_src)
+    cfg = dataclasses.replace(cfg, freq_hz=freq, noise_sigma_jy=noise_scale * cfg.noise_sigma_jy)
     o = synth.observation(3, cfg)
     cat = synth.catalogue(cfg, np.random.default_rng(seed))
     rng = np.random.default_rng(seed + 1)
@@ -203,3 +205,131 @@ def test_batched_full_size_config3(ctx):
     f2.free()
     f.free()
     mctx.close()
+
+
+def _robust_rejection(seen, box, stride, lmax):
+    """The oracle's window decision, or None where moving the threshold by a
+    few LL_RTOL changes it (two correct FP64 evaluations may then differ)."""
+    d = 3 * G.LL_RTOL * max(1.0, abs(lmax)) * 4
+    lo = oracle.window_rejected(seen, box, stride, oracle.Params(frac=0.05 * math.exp(-d)))
+    hi = oracle.window_rejected(seen, box, stride, oracle.Params(frac=0.05 * math.exp(+d)))
+    return lo if lo == hi else None
+
+
+def _secondary_peak_box(full, argmax, p=oracle.Params()):
+    """The smallest square box around a local maximum (over the 8 neighbours)
+    other than the global one that the neighbour rule alone trusts, or None:
+    a window the lattice check has to catch."""
+    n = p.n_e
+    s = full.reshape(n, n)
+    pad = np.full((n + 2, n + 2), -np.inf)
+    pad[1:-1, 1:-1] = s
+    peak = np.isfinite(s)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            if di or dj:
+                peak &= s > pad[1 + di:n + 1 + di, 1 + dj:n + 1 + dj]
+    g1, g2 = divmod(argmax, n)
+    for idx in np.flatnonzero(peak.reshape(-1)):
+        if idx == argmax:
+            continue
+        i1, i2 = divmod(int(idx), n)
+        for h in range(1, 25):
+            b = (max(0, i1 - h), min(n - 1, i1 + h), max(0, i2 - h), min(n - 1, i2 + h))
+            if b[0] <= g1 <= b[1] and b[2] <= g2 <= b[3]:
+                break
+            if not oracle.window_rejected(full, b, 0, p):
+                return b
+    return None
+
+
+def _check_window_rule(ctx, noise_scale, seed, strides, box_for):
+    """Fit a 40-source field with the boxes box_for(s, full_surface,
+    full_estimate, rng) and fallback + lattice check; every robust decision
+    and every kept or refitted result must match the oracle.  Returns
+    (decisions checked, refits, refits by the lattice alone)."""
+    cfg, o, cat, data = _field(n_src=40, seed=seed, noise_scale=noise_scale)
+    catc = G.circular(cat)
+    obs = G.make_obs(o, data)
+    f = ctx.facets_create(obs, catc)
+    ctx.extract_facets(obs, catc, None, f)
+    resid_o = data - oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, catc)
+    fac_o = [G.oracle_facet(o, resid_o, catc, s) for s in range(cat.n_src)]
+    full = [oracle.fit_source(fac_o[s], cat.flux_jy[s]) for s in range(cat.n_src)]
+    rng = np.random.default_rng(seed + 1)
+    n_checked = n_refit = n_lattice = 0
+    for stride in strides:
+        boxes = []
+        for s in range(cat.n_src):
+            b = box_for(s, full[s][0], full[s][1], rng)
+            if b is None:
+                h1, h2 = rng.integers(1, 13, 2)
+                c1, c2 = rng.integers(0, 81, 2)
+                b = (max(0, c1 - h1), min(80, c1 + h1), max(0, c2 - h2), min(80, c2 + h2))
+            boxes.append(tuple(int(v) for v in b))
+        out = G.fit_out_tensors(cat.n_src, surface=False)
+        ctx.fit_sources(f, out, mode=1, window=_window_tensor(boxes), fallback=True, check_stride=stride)
+        ctx.sync()
+        h = G.host(out)
+        for s in range(cat.n_src):
+            if fac_o[s].n_cells == 0:
+                continue
+            surf_w, est_w = oracle.fit_source(fac_o[s], cat.flux_jy[s], window=boxes[s])
+            seen = full[s][0].copy()
+            seen[np.isfinite(surf_w)] = surf_w[np.isfinite(surf_w)]
+            lmax = est_w.lmax if math.isfinite(est_w.lmax) else 0.0
+            want = _robust_rejection(seen, boxes[s], stride, lmax)
+            if want is None:
+                continue
+            n_checked += 1
+            assert bool(h["flags"][s] & rlf.RLF_FLAG_FALLBACK) == want, (stride, s, boxes[s])
+            if want:
+                n_refit += 1
+                n_lattice += not _robust_rejection(seen, boxes[s], 0, lmax)
+                variants = G.oracle_estimate_variants(full[s][0])
+                for e in variants:
+                    e.flags |= rlf.RLF_FLAG_FALLBACK
+                G.check_fit(h, s, full[s][0], variants)
+            else:
+                G.check_fit(h, s, surf_w, G.oracle_estimate_variants(surf_w))
+    f.free()
+    return n_checked, n_refit, n_lattice
+
+
+def test_window_rule_with_lattice_check_against_oracle(ctx):
+    """The fallback decision (neighbour rule + lattice check, strides 4 and
+    3) agrees with the oracle's; kept and refitted results match the oracle.
+    A low-noise field (compact posteriors) with boxes around the maximum of
+    random size, and a field at the nominal noise with boxes around
+    secondary likelihood peaks that only the lattice check rejects."""
+    def around_max(s, surf, est, rng):
+        if s % 2 or est.argmax < 0:
+            return None
+        i1, i2 = divmod(est.argmax, 81)
+        h1, h2 = rng.integers(6, 31, 2)
+        return (max(0, i1 - h1), min(80, i1 + h1), max(0, i2 - h2), min(80, i2 + h2))
+
+    def secondary(s, surf, est, rng):
+        return _secondary_peak_box(surf, est.argmax) if est.argmax >= 0 else None
+
+    a = _check_window_rule(ctx, 0.02, 61, (4, 3), around_max)
+    b = _check_window_rule(ctx, 1.0, 61, (4,), secondary)
+    print(f"window rule: low noise {a}, nominal noise {b} (checked, refits, lattice-only refits)")
+    assert a[0] >= 70 and 0 < a[1] < a[0]
+    assert b[0] >= 35 and b[2] >= 2
+
+
+def test_check_stride_argument_errors(ctx):
+    cfg, o, cat, data = _field(n_src=4, seed=71)
+    obs = G.make_obs(o, data)
+    f = ctx.facets_create(obs, cat)
+    out = G.fit_out_tensors(cat.n_src, surface=False)
+    win = _window_tensor([(30, 50, 30, 50)] * cat.n_src)
+    for kw in (dict(mode=1, window=win, fallback=False, check_stride=4),     # needs the fallback
+               dict(mode=0, check_stride=4),                                  # needs a window
+               dict(mode=1, window=win, fallback=True, check_stride=1),
+               dict(mode=1, window=win, fallback=True, check_stride=81),
+               dict(mode=1, window=win, fallback=True, check_stride=-2)):
+        with pytest.raises(rlf.RlfError):
+            ctx.fit_sources(f, out, **kw)
+    f.free()

@@ -112,15 +112,26 @@ def test_windows_match_oracle(ctx):
     net.windows(yd, w, nsigma=3.0, min_half=3)
     ctx.sync()
     assert np.array_equal(w.cpu().numpy(), M.windows(y, 3.0, 81, 0.02, 3))
+    net.windows(yd, w, nsigma=2.5, min_half=2, full_frac=0.1)
+    ctx.sync()
+    ref = M.windows(y, 2.5, 81, 0.02, 2, full_frac=0.1)
+    assert np.array_equal(w.cpu().numpy(), ref)
+    assert 0 < np.count_nonzero(ref[:, 1] - ref[:, 0] == 80) < 500
     net.free()
 
 
-def test_features_match_oracle_facets(ctx):
+@pytest.mark.parametrize("freq", [None, (0.95e9, 1.05e9, 1.15e9)])
+def test_features_match_oracle_facets(ctx, freq):
+    """One channel at the reference frequency (g = 1) and three channels
+    below it (g = mean spectral factor > 1)."""
+    import dataclasses
     torch = G.torch_cuda()
     cfg = synth.CONFIGS[0]
-    o = synth.observation(0)
+    if freq is not None:
+        cfg = dataclasses.replace(cfg, freq_hz=freq)
+    o = synth.observation(0, cfg)
     cat = synth.catalogue(cfg, synth.rng(0, synth.STREAM_CAT))
-    nz = synth.noise(cfg, synth.rng(0, synth.STREAM_NOISE), o.n_rows)
+    nz = synth.noise(cfg, synth.rng(0, synth.STREAM_NOISE), o.n_rows * o.n_chan)
     obs = G.make_obs(o, nz)
     f = ctx.facets_create(obs, cat)
     ctx.extract_facets(obs, cat, obs.vis, f)
@@ -129,9 +140,11 @@ def test_features_match_oracle_facets(ctx):
     net.features(f, x)
     ctx.sync()
     got = x.to(torch.float32).cpu().numpy().astype(np.float64)
+    g = M.spectral_norm(o.freq_hz)
+    assert (g == 1.0) == (freq is None)
     for s in range(cat.n_src):
         fac = G.oracle_facet(o, nz, cat, s)
-        ref = M.bf16(M.features(fac.ix, fac.iy, fac.vbar, cat.flux_jy[s]))
+        ref = M.bf16(M.features(fac.ix, fac.iy, fac.vbar, cat.flux_jy[s] * g))
         assert np.mean(got[s] != ref) < 1e-3, s      # BF16 ties of values equal to ~1e-12 may round apart
         assert np.max(np.abs(got[s] - ref)) <= 2 ** -7 * np.max(np.abs(ref))
     net.free()
@@ -172,3 +185,28 @@ def test_training_reduces_loss_and_resumes_bit_exactly(ctx):
     assert a["step"] == c["step"] == 65
     net.free()
     net2.free()
+
+
+def test_variance_floor_in_the_head(ctx):
+    """Log-variance outputs far below the floor: the loss is the oracle's
+    floored loss and no gradient reaches the log-variance outputs."""
+    torch = G.torch_cuda()
+    p = _init(14)
+    p["b4"][3:] = -20.0
+    rng = np.random.default_rng(15)
+    n = 64
+    x = M.bf16(rng.standard_normal((n, M.N_IN)) * 0.2)
+    t = rng.standard_normal((n, 3)) * 0.01
+    net = rlf.Mlp(ctx, max_batch=64)
+    net.set_state(M.pack(p))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    net.train_step(_bf16_tensor(x), torch.from_numpy(t.astype(np.float32)).to("cuda:0"), 1e-4, loss)
+    ctx.sync()
+    y, cache = M.forward(x, p)
+    assert np.all(y[:, 3:] < M.S_MIN - 5)
+    t32 = t.astype(np.float32).astype(np.float64)
+    assert loss.item() == pytest.approx(M.loss(y, t32), rel=1e-4)
+    gg = M.unpack(net.get_state()["grad"])
+    assert np.all(gg["b4"][3:] == 0.0) and np.all(gg["W4"][:, 3:] == 0.0)
+    assert np.any(gg["b4"][:3] != 0.0)
+    net.free()

@@ -107,11 +107,59 @@ def test_features_layout():
 
 
 def test_windows_hand_case():
-    y = np.array([[0.1, -0.3, 0.0, math.log(0.02 ** 2), math.log(0.05 ** 2), 0.0],
+    y = np.array([[0.1, -0.3, 0.0, math.log(0.05 ** 2), math.log(0.05 ** 2), 0.0],
                   [0.79, 0.0, 0.0, math.log(1e-6), math.log(1e-6), 0.0]])
     w = mlp.windows(y, nsigma=3.0, min_half=3)
-    # e1: 0.1 +- 0.06 -> grid (0.04/0.02 + 40, 0.16/0.02 + 40) = (42, 48);
+    # e1: 0.1 +- 0.15 -> grid (-0.05/0.02 + 40, 0.25/0.02 + 40) = (37.5, 52.5) -> (37, 53);
     # e2: -0.3 +- 0.15 -> (-0.45/0.02 + 40, -0.15/0.02 + 40) = (17.5, 32.5) -> (17, 33)
-    assert w[0].tolist() == [42, 48, 17, 33]
-    # tiny sigma: +-3 steps around the nearest point, clamped to the grid
-    assert w[1].tolist() == [77, 80, 37, 43]
+    assert w[0].tolist() == [37, 53, 17, 33]
+    # tiny predicted variance: floored at 1e-3, sd 0.0316, +-0.0949 ->
+    # e1 (74.75, 84.74) -> (74, 80 clamped); e2 (35.26, 44.74) -> (35, 45)
+    assert w[1].tolist() == [74, 80, 35, 45]
+
+
+def test_variance_floor_matches_torch_clamp_and_stops_the_gradient():
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal((9, 6))
+    y[:4, 3:] = mlp.S_MIN - rng.uniform(0.5, 5.0, (4, 3))         # predictions below the floor
+    t = rng.standard_normal((9, 3)) * 0.1
+    ref = torch.nn.GaussianNLLLoss(full=False, eps=1e-3, reduction="mean")(
+        torch.tensor(y[:, :3]), torch.tensor(t), torch.tensor(np.exp(y[:, 3:]))).item()
+    assert mlp.loss(y, t) == pytest.approx(3 * ref, rel=1e-12)
+    # the loss no longer depends on s below the floor; above it, it does
+    h = 1e-6
+    for i, d in ((0, 3), (2, 5), (6, 4), (8, 3)):
+        yp, ym = y.copy(), y.copy()
+        yp[i, d] += h
+        ym[i, d] -= h
+        fd = (mlp.loss(yp, t) - mlp.loss(ym, t)) / (2 * h)
+        assert (fd == 0.0) == (i < 4)
+    # b4's gradient is the batch mean of dL/dy: rows below the floor add nothing to the s columns
+    p = _params(8)
+    x = rng.standard_normal((9, mlp.N_IN)) * 0.3
+    yy, cache = mlp.forward(x, p, round_bf16=False)
+    cache["y"] = y
+    g = mlp.backward(p, cache, t, round_bf16=False)
+    above = y[4:, 3:]
+    expect = np.sum(0.5 * (1.0 - (t[4:] - y[4:, :3]) ** 2 * np.exp(-above)), axis=0) / 9
+    assert np.allclose(g["b4"][3:], expect, rtol=1e-12, atol=0)
+
+
+def test_spectral_norm():
+    assert mlp.spectral_norm([1.4e9]) == 1.0
+    assert mlp.spectral_norm([0.7e9, 1.4e9]) == pytest.approx((2 ** 0.7 + 1.0) / 2, rel=1e-15)
+    assert mlp.spectral_norm([2.8e9], beta=-1.0) == pytest.approx(0.5, rel=1e-15)
+
+
+def test_features_are_clipped():
+    x = mlp.features(np.array([0, 1]), np.array([0, 0]), np.array([100 - 3j, -50 + 2j]), 10.0)
+    assert x[32 * 64 + 32] == 4.0 and x[4096 + 32 * 64 + 32] == -0.3
+    assert x[32 * 64 + 33] == -4.0 and x[4096 + 32 * 64 + 33] == 0.2
+
+
+def test_windows_full_grid_above_area_fraction():
+    y = np.array([[0.1, -0.3, 0.0, math.log(0.05 ** 2), math.log(0.05 ** 2), 0.0]])
+    # the box (37..53) x (17..33) holds 17 * 17 = 289 points = 0.04405 of 81^2
+    assert mlp.windows(y, full_frac=0.0441)[0].tolist() == [37, 53, 17, 33]
+    assert mlp.windows(y, full_frac=0.0440)[0].tolist() == [0, 80, 0, 80]
+    assert mlp.windows(y, full_frac=0.0)[0].tolist() == [0, 80, 0, 80]

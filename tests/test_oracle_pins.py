@@ -499,3 +499,72 @@ def test_alpha_marginalisation_against_scipy_logsumexp():
     L = np.stack([oracle.loglike_alpha(f, e1, e2, a) for a in knots], 0)
     assert np.max(L) > 1e3
     assert np.allclose(got, logsumexp(L + logw[:, None], axis=0), rtol=1e-14, atol=1e-10)
+
+
+# ---- the narrowed fit's window rule (not in the paper) ----------------------
+
+def _two_bumps(p, big=(20, 20), small=(55, 55), h_small=-1.0, width=3.0):
+    """Synthetic ln L surface: two Gaussian bumps on the valid grid, the
+    larger (height 0) at `big`, the smaller (height h_small) at `small`."""
+    i1, i2, _, _, valid = oracle.e_grid(p.n_e, p.e_step)
+    g = lambda c: -((i1 - c[0]) ** 2 + (i2 - c[1]) ** 2) / (2 * width ** 2)
+    s = np.logaddexp(g(big), h_small + g(small))
+    return np.where(valid, s, -np.inf)
+
+
+def test_window_rule_hand_cases():
+    p = oracle.Params()
+    s = _two_bumps(p)
+    # a box around the larger bump holding its whole 5 % set: trusted
+    assert not oracle.window_rejected(s, (10, 30, 10, 30), 0, p)
+    # the same box cut through the set: a member has a neighbour outside
+    assert oracle.window_rejected(s, (20, 30, 10, 30), 0, p)
+    # a box around the smaller bump: its own set is interior, trusted without
+    # the lattice; with stride 4 the lattice point (20, 20) (offset -20 from
+    # the centre 40 on both axes) sits at the larger bump and rejects it
+    assert not oracle.window_rejected(s, (45, 65, 45, 65), 0, p)
+    assert oracle.window_rejected(s, (45, 65, 45, 65), 4, p)
+    # stride 3: offsets -21 and -18 on each axis bracket the bump at -20
+    # (distance^2 = 1 + 1 = 2 -> ln L = -2/18): still above the threshold
+    assert oracle.window_rejected(s, (45, 65, 45, 65), 3, p)
+    # a bump far below the window's threshold is not a reason to refit
+    s2 = _two_bumps(p, h_small=+4.0)           # the window's bump is now the larger by e^4 > 1/0.05
+    assert not oracle.window_rejected(s2, (45, 65, 45, 65), 4, p)
+    # a window holding no valid point (a corner beyond |e| = 1)
+    assert oracle.window_rejected(s, (0, 3, 0, 3), 0, p)
+    # the domain edge is not a window edge: the full grid is never rejected
+    assert not oracle.window_rejected(s, (0, 80, 0, 80), 4, p)
+
+
+def test_window_rule_brute_force_on_tiny_grid():
+    """Against a direct reading of the rule, point by point, on a 21x21 grid
+    (e_step 0.1) with random surfaces and boxes."""
+    p = oracle.Params(n_e=21, e_step=0.1)
+    rng = np.random.default_rng(3)
+    i1, i2, _, _, valid = oracle.e_grid(p.n_e, p.e_step)
+    ctr = 10
+    for trial in range(300):
+        s = np.where(valid, rng.normal(0, 1.5, p.n_e * p.n_e), -np.inf)
+        a, b = sorted(rng.integers(0, 21, 2))
+        c, d = sorted(rng.integers(0, 21, 2))
+        S = int(rng.choice([0, 2, 3, 4]))
+        box = lambda x, y: a <= x <= b and c <= y <= d
+        ok = lambda x, y: 0 <= x < 21 and 0 <= y < 21 and (x - ctr) ** 2 + (y - ctr) ** 2 < 100
+        pts = [(x, y) for x in range(21) for y in range(21) if ok(x, y) and box(x, y)]
+        if not pts:
+            expect = True
+        else:
+            thr = max(s[x * 21 + y] for x, y in pts) + math.log(0.05)
+            expect = False
+            for x, y in pts:
+                if s[x * 21 + y] >= thr:
+                    for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                        if ok(x + dx, y + dy) and not box(x + dx, y + dy):
+                            expect = True
+            if S:
+                for x in range(21):
+                    for y in range(21):
+                        if ok(x, y) and not box(x, y) and (x - ctr) % S == 0 and (y - ctr) % S == 0 \
+                                and s[x * 21 + y] >= thr:
+                            expect = True
+        assert oracle.window_rejected(s, (a, b, c, d), S, p) == expect, trial

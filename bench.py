@@ -34,6 +34,21 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
 #   D += W Re(Vbar) f (FMA), Mm += (W f) f (MUL + FMA)                      = 10
 FIT_FLOP_CELL_POINT = 9
 FIT_FLOP_CELL_POINT_KNOT = 10
+# Algorithmic FLOPs per (visibility, source) pair, FMA = 2 and one per
+# elementary function value (sin, cos, x^{-3/2}, round to integer):
+#   extraction: phase u l + v m + w n1 (MUL + 2 FMA) 5, sin + cos 2,
+#     residual * exp(-i phase) (2 MUL + 2 FMA) 6, profile argument
+#     1 + q11 u^2 + q12 uv + q22 v^2 (3 FMA; u^2, uv, v^2 once per visibility) 6,
+#     x^{-3/2} 1, + spec S f (MUL + FMA) 3, cell index (2 MUL + 2 round) 4,
+#     W += w, Z += w z (ADD + 2 FMA) 5                                        = 32
+#   sky-model DFT: phase 5, sin + cos 2, profile argument 6, x^{-3/2} 1,
+#     S f (MUL) 1, sum += amp (cos, sin) (2 FMA) 4                             = 19
+EXTRACT_FLOP_PAIR = 32
+MODEL_FLOP_PAIR = 19
+# HBM bytes per launch of the dominant kernel (extraction) at this workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by a plain copy's
+# reading), for the kernel as it is now; None where not measured.
+EXTRACT_TRAFFIC_BYTES = {"fp64": None, "mixed": None}
 
 
 def log(*a):
@@ -115,6 +130,7 @@ def main():
         "ms_per_step": other_form["json"]["ms_per_step"], "stage_ms": other_form["json"]["stage_ms"],
         "gvis_per_s_extract": other_form["json"]["gvis_per_s_extract"],
         "roofline": other_form["json"]["roofline"],
+        "kernel_rooflines": other_form["json"]["kernel_rooflines"],
         "max_abs_de_vs_" + args.precision: float(de),
         "note": "same synthetic field; the mixed form takes complex64 visibilities and f32 weights",
     }
@@ -336,10 +352,29 @@ def run_form(precision, steps, warmup):
     cells = np.diff(fc["offsets"])
     n_valid = 6333
     n_vis = o.n_rows * o.n_chan
-    flops = float(np.sum(cells)) * n_valid * (FIT_FLOP_CELL_POINT + FIT_FLOP_CELL_POINT_KNOT * p.num_r)
-    fit_s = stage_ms[2] * 1e-3
     peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
-    achieved = flops / fit_s / 1e12
+    pairs = float(n_vis) * n
+
+    def roof(name, flop, ms, note):
+        a = flop / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": round(a, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(a / peak, 4), "algorithmic_flop": flop, "note": note}
+
+    kernels = {
+        "extract": roof("facet extraction (k_extract; the stage also runs the sorted-order gather and compaction, "
+                        "<2 % of it)", EXTRACT_FLOP_PAIR * pairs, stage_ms[1],
+                        f"{EXTRACT_FLOP_PAIR} FLOP per (visibility, source) pair x {pairs:.4g} pairs"),
+        "fit": roof("likelihood grid (k_fit) + estimator",
+                    float(np.sum(cells)) * n_valid * (FIT_FLOP_CELL_POINT + FIT_FLOP_CELL_POINT_KNOT * p.num_r),
+                    stage_ms[2], f"{FIT_FLOP_CELL_POINT} FLOP per (cell, e point) + {FIT_FLOP_CELL_POINT_KNOT} per "
+                                 f"(cell, e point, knot) x {int(np.sum(cells))} cells x {n_valid} x {p.num_r}"),
+        "model": roof("sky-model residual DFT (k_model)", MODEL_FLOP_PAIR * pairs, stage_ms[0],
+                      f"{MODEL_FLOP_PAIR} FLOP per (visibility, source) pair x {pairs:.4g} pairs"),
+    }
+    dominant = max(("extract", "fit", "model"), key=lambda k: {"model": stage_ms[0], "extract": stage_ms[1],
+                                                               "fit": stage_ms[2]}[k])
+    roofline = dict(kernels[dominant])
+    roofline["traffic"] = EXTRACT_TRAFFIC_BYTES[precision] if dominant == "extract" else None
     flags = out["flags"].cpu().numpy()
     e1 = out["e1"].cpu().numpy()
     e2 = out["e2"].cpu().numpy()
@@ -369,10 +404,8 @@ def run_form(precision, steps, warmup):
         "vis_ingest_per_s": round(n_vis / (ms_per_step * 1e-3), 1),
         "stage_ms": {"model_vis": round(stage_ms[0], 4), "extract": round(stage_ms[1], 4),
                      "fit": round(stage_ms[2], 4)},
-        "roofline": {"kernel": "likelihood grid (k_fit) + estimator", "bound": "alu",
-                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "algorithmic_flop": flops},
+        "roofline": roofline,
+        "kernel_rooflines": kernels,
         "facet_cells": {"total": int(cells.sum()), "mean": round(float(cells.mean()), 1),
                         "min": int(cells.min()), "max": int(cells.max())},
         "fit_quality": {"rms_e_minus_true": round(rms, 5), "bad_var": int(np.sum(flags & 1)),

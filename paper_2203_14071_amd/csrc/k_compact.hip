@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_count(CompactArgs a) {
   const SrcGeom g = a.geom[s];
   const int64_t n = (int64_t)g.side * g.side;
   int local = 0;
-  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) local += a.acc.count[g.base + k] > 0u;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) local += a.acc.cell[g.base + k].w > 0.0;
   const int t = block_sum_int(local, sh);
   if (threadIdx.x == 0) a.cells.n_nonempty[s] = t;
 }
@@ -71,15 +71,13 @@ __global__ __launch_bounds__(256) void k_write(CompactArgs a) {
     double W = 0.0, zr = 0.0, zi = 0.0;
     if (k < n) {
       const int64_t d = g.base + k;
-      cnt = a.acc.count[d];
+      const double4 c = a.acc.cell[d];
+      cnt = (uint32_t)c.w;                       // an exact integer sum
       if (cnt) {
-        W = a.acc.wsum[d];
-        zr = a.acc.zre[d];
-        zi = a.acc.zim[d];
-        a.acc.count[d] = 0u;
-        a.acc.wsum[d] = 0.0;
-        a.acc.zre[d] = 0.0;
-        a.acc.zim[d] = 0.0;
+        W = c.x;
+        zr = c.y;
+        zi = c.z;
+        a.acc.cell[d] = make_double4(0.0, 0.0, 0.0, 0.0);
       }
     }
     const bool keep = cnt > 0u;

@@ -2,7 +2,7 @@
 // residual to the source, add back the source's own model, and accumulate the
 // weighted result into the source's facet cell (rint(u theta), rint(v theta)).
 //
-// Work decomposition.  Lanes are sources: a wave holds 64 sources (one per
+// Work decomposition.  Lanes are sources: a wave holds 64 NS sources (NS per
 // lane, their constants in VGPRs) and walks a chunk of visibilities in the
 // facet object's uv-sorted order; each visibility's data is uniform across
 // the wave and arrives through scalar loads.  Along the sorted order every
@@ -15,7 +15,8 @@
 // tiles) land on one XCD and share its L2 for the chunk's data.
 //
 // Integer results are exact (cell index in FP64 exactly as rint(fl(u theta)));
-// FP sums are atomic and order-dependent in their last bits.
+// FP sums are atomic and order-dependent in their last bits.  Runs are summed
+// in FP64 in both forms (the mixed form's FP32 terms are widened per term).
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
 
@@ -24,38 +25,65 @@ namespace rlf {
 namespace {
 
 constexpr int kXcd = 8;
-constexpr int kWaves = 4;          // waves (source tiles) per block
-constexpr int kGroup = 4;          // visibilities whose scalar loads are issued together
+constexpr int kWaves = 4;          // waves per block
+constexpr int kNsF64 = 2, kNsMixed = 2;        // sources per lane
+constexpr int kGroupF64 = 2, kGroupMixed = 4;  // visibilities whose scalar loads are issued together
+constexpr double kNoRun = -0.5;    // run key meaning "no run" (keys are integers)
 
-struct Run {
-  int key;                         // cell in the source's dense block, -1 = none
-  uint32_t n;
-  double w, zr, zi;
+// One source of a lane: facet geometry and the open run.
+struct LaneSrc {
+  bool active;
+  int64_t base;
+  double half, side, koff;         // key = iy side + ix + koff
+  double key, rw, rzr, rzi, rn;
 };
 
-__device__ __forceinline__ void flush(uint32_t *__restrict__ cnt, double *__restrict__ ws, double *__restrict__ zre,
-                                      double *__restrict__ zim, int64_t base, const Run &p) {
-  const int64_t k = base + p.key;
-  atomicAdd(cnt + k, p.n);
-  unsafeAtomicAdd(ws + k, p.w);
-  unsafeAtomicAdd(zre + k, p.zr);
-  unsafeAtomicAdd(zim + k, p.zi);
+// Add the open run to its dense cell: four FP64 atomics at one address (the
+// count is an exact integer in FP64).
+__device__ __forceinline__ void flush(double4 *__restrict__ acc, const LaneSrc &L) {
+  double *c = &acc[L.base + (int32_t)L.key].x;
+  unsafeAtomicAdd(c, L.rw);
+  unsafeAtomicAdd(c + 1, L.rzr);
+  unsafeAtomicAdd(c + 2, L.rzi);
+  unsafeAtomicAdd(c + 3, L.rn);
+}
+
+__device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, double ww, double xf,
+                                     double yf, double zr, double zi) {
+  const double k = fma(yf, L.side, xf + L.koff);
+  if (k != L.key) {
+    if (L.key >= 0.0 && L.active) flush(acc, L);
+    const bool inb = fabs(xf) <= L.half && fabs(yf) <= L.half;
+    if (!inb && L.active) atomicOr(err, 1u);
+    L.key = inb ? k : kNoRun;
+    L.rn = L.rw = L.rzr = L.rzi = 0.0;
+  }
+  L.rn += 1.0;
+  L.rw += ww;
+  L.rzr = fma(ww, zr, L.rzr);
+  L.rzi = fma(ww, zi, L.rzi);
 }
 
 // The read-only visibility data and the atomic targets are separate
 // restrict-qualified kernel parameters: with no possible aliasing the
 // compiler keeps the per-visibility loads scalar (s_load) although the loop
-// issues atomics.  Visibilities are taken in groups of kGroup whose loads are
-// issued together; the sorted arrays are padded so a group never reads past
-// the end, and padding carries weight 0.
-template <bool kMixed>
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double *__restrict__ su,
-                                                 const double *__restrict__ sv, const double *__restrict__ sw,
-                                                 const uint32_t *__restrict__ sch4, const void *__restrict__ sres,
-                                                 const void *__restrict__ swt, const double *__restrict__ spec_tab,
-                                                 uint32_t *__restrict__ cnt, double *__restrict__ ws,
-                                                 double *__restrict__ zre, double *__restrict__ zim) {
-  __shared__ double2 tab[kCisTable + 1];
+// issues atomics.  Per visibility the wave loads (u, v, w, spec), the
+// profile's quadratic terms, the residual and the weight; flagged
+// visibilities carry weight +0 and are skipped on a scalar test of the bits.
+// A lane may hold NS sources (NS * 64 per wave) to share each load.
+//
+// Cell index: ix = rint(fl(u theta)) and iy likewise, in FP64 (exact
+// integers); the run key (iy + half) side + (ix + half) is formed in FP64 too
+// (exact: |key| < 2^31) and compared as a double, so the common path has no
+// conversions.  The facet half-size was sized on the host from the largest
+// |u|, |v| with the same rounding chain, so every index is inside its facet;
+// the bound is still checked whenever a run starts (err bit 0).
+template <bool kMixed, int NS, int G>
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
+                                                 const void *__restrict__ squad, const void *__restrict__ sres,
+                                                 const uint64_t *__restrict__ swt,
+                                                 double4 *__restrict__ acc) {
+  __shared__ double2 tab[kMixed ? 1 : kCisTable + 1];
   if (!kMixed) {
     cis_table_init(tab);
     __syncthreads();
@@ -68,133 +96,125 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double *__
   const int tile = (int)(local % bpc) * kWaves + wid;
   if (chunk >= a.n_chunks || tile >= a.n_tiles) return;          // uniform per wave
 
-  const int s_raw = tile * 64 + lane;
-  const bool active = s_raw < a.n_src;
-  const int s = active ? s_raw : a.n_src - 1;
-  const SrcGeom g = a.geom[s];
+  LaneSrc L[NS];
+  int src[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int s_raw = (tile * NS + i) * 64 + lane;
+    L[i].active = s_raw < a.n_src;
+    src[i] = L[i].active ? s_raw : a.n_src - 1;
+    const SrcGeom g = a.geom[src[i]];
+    L[i].base = g.base;
+    L[i].half = (double)g.half;
+    L[i].side = (double)g.side;
+    L[i].koff = L[i].half * (L[i].side + 1.0);
+    L[i].key = kNoRun;
+    L[i].rn = L[i].rw = L[i].rzr = L[i].rzi = 0.0;
+  }
   const int64_t j0 = chunk * (int64_t)a.chunk;
-  const int64_t j1 = min(a.sv.n_vis, j0 + (int64_t)a.chunk);
-  const bool multi = a.n_chan > 1;
+  const int len = (int)(min(a.sv.n_vis, j0 + (int64_t)a.chunk) - j0);
+  const double4 *__restrict__ geo = sgeo + j0;
+  const uint64_t *__restrict__ wt = swt + j0;                    // weight bits: 0 = skip
 
-  Run cur{-1, 0u, 0.0, 0.0, 0.0};
   if (!kMixed) {
-    const SrcModel p = a.src[s];
-    const double2 *__restrict__ res = reinterpret_cast<const double2 *>(sres);
-    const double *__restrict__ wt = reinterpret_cast<const double *>(swt);
-    for (int64_t jg = j0; jg < j1; jg += kGroup) {
-      double wwg[kGroup], ug[kGroup], vg[kGroup], wg[kGroup], spg[kGroup];
-      double2 rg[kGroup];
-      const uint32_t chg = multi ? sch4[jg / 4] : 0u;
+    SrcModel p[NS];
+    double sflux[NS];
 #pragma unroll
-      for (int t = 0; t < kGroup; ++t) {
-        wwg[t] = wt[jg + t];
-        ug[t] = su[jg + t];
-        vg[t] = sv[jg + t];
-        wg[t] = sw[jg + t];
-        rg[t] = res[jg + t];
-        spg[t] = spec_tab[(chg >> (8 * t)) & 0xffu];
+    for (int i = 0; i < NS; ++i) {
+      p[i] = a.src[src[i]];
+      sflux[i] = kPowM32Scale * p[i].flux;
+    }
+    const double4 *__restrict__ quad = reinterpret_cast<const double4 *>(squad) + j0;
+    const double2 *__restrict__ res = reinterpret_cast<const double2 *>(sres) + j0;
+    for (int jl = 0; jl < len; jl += G) {
+      double4 gg[G], qg[G];
+      double2 rg[G];
+      uint64_t wwg[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        gg[t] = geo[jl + t];
+        qg[t] = quad[jl + t];
+        rg[t] = res[jl + t];
+        wwg[t] = wt[jl + t];
       }
 #pragma unroll
-      for (int t = 0; t < kGroup; ++t) {
-      const double ww = wwg[t];
-      if (!(ww > 0.0)) continue;                                   // uniform
-      const double u = ug[t], v = vg[t], w = wg[t];
-      const double2 r = rg[t];
-      const double spec = spg[t];
-      const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
-      const double2 cs = cis2pi_f64(ph, tab);
-      double zr = fma(r.x, cs.x, r.y * cs.y);                      // residual * exp(-2 pi i ph)
-      const double zi = fma(r.y, cs.x, -(r.x * cs.y));
-      const double x = fma(p.q11, u * u, fma(p.q12x2, u * v, fma(p.q22, v * v, 1.0)));
-      const double q = rsqrt_f64(x);
-      zr = fma(spec * p.flux, q * q * q, zr);                      // own model, real after the shift
-      const int ix = (int)rint(__dmul_rn(u, p.theta));
-      const int iy = (int)rint(__dmul_rn(v, p.theta));
-      const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
-      const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
-      const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
-      if (key != cur.key) {
-        if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
-        if (!inb && active) atomicOr(a.err, 1u);
-        cur.key = key;
-        cur.n = 0u;
-        cur.w = cur.zr = cur.zi = 0.0;
-      }
-      cur.n += 1u;
-      cur.w += ww;
-      cur.zr = fma(ww, zr, cur.zr);
-      cur.zi = fma(ww, zi, cur.zi);
+      for (int t = 0; t < G; ++t) {
+        if (jl + t >= len) break;                                   // uniform
+        if (wwg[t] == 0u) continue;                                  // uniform: flagged or padding
+        const double u = gg[t].x, v = gg[t].y, ww = __longlong_as_double((long long)wwg[t]);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
+          const double2 cs = cis2pi_f64(ph, tab);
+          double zr = fma(rg[t].x, cs.x, rg[t].y * cs.y);           // residual * exp(-2 pi i ph)
+          const double zi = fma(rg[t].y, cs.x, -(rg[t].x * cs.y));
+          const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, 1.0)));
+          zr = fma(gg[t].w * sflux[i], pow_m32_f64(x), zr);         // own model, real after the shift
+          step(L[i], acc, a.err, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
+               zr, zi);
+        }
       }
     }
   } else {
-    const SrcMixed p = a.src32[s];
-    const float2 *__restrict__ res = reinterpret_cast<const float2 *>(sres);
-    const float *__restrict__ wt = reinterpret_cast<const float *>(swt);
-    for (int64_t jg = j0; jg < j1; jg += kGroup) {
-      float wwg[kGroup];
-      double ug[kGroup], vg[kGroup], wg[kGroup], spg[kGroup];
-      float2 rg[kGroup];
-      const uint32_t chg = multi ? sch4[jg / 4] : 0u;
+    SrcMixed p[NS];
 #pragma unroll
-      for (int t = 0; t < kGroup; ++t) {
-        wwg[t] = wt[jg + t];
-        ug[t] = su[jg + t];
-        vg[t] = sv[jg + t];
-        wg[t] = sw[jg + t];
-        rg[t] = res[jg + t];
-        spg[t] = spec_tab[(chg >> (8 * t)) & 0xffu];
+    for (int i = 0; i < NS; ++i) p[i] = a.src32[src[i]];
+    const float4 *__restrict__ quad = reinterpret_cast<const float4 *>(squad) + j0;
+    const float2 *__restrict__ res = reinterpret_cast<const float2 *>(sres) + j0;
+    for (int jl = 0; jl < len; jl += G) {
+      double4 gg[G];
+      float4 qg[G];
+      float2 rg[G];
+      uint64_t wwg[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        gg[t] = geo[jl + t];
+        qg[t] = quad[jl + t];
+        rg[t] = res[jl + t];
+        wwg[t] = wt[jl + t];
       }
 #pragma unroll
-      for (int tt = 0; tt < kGroup; ++tt) {
-      const float ww = wwg[tt];
-      if (!(ww > 0.0f)) continue;                                  // uniform
-      const double u = ug[tt], v = vg[tt], w = wg[tt];
-      const float2 r = rg[tt];
-      const float spec = (float)spg[tt];
-      const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
-      const float t = (float)(ph - rint(ph));                      // turns, |t| <= 1/2
-      const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
-      float zr = fmaf(r.x, cs, r.y * sn);
-      const float zi = fmaf(r.y, cs, -(r.x * sn));
-      const float uf = (float)u, vf = (float)v;
-      const float x = fmaf(p.q11, uf * uf, fmaf(p.q12x2, uf * vf, fmaf(p.q22, vf * vf, 1.0f)));
-      const float q = __builtin_amdgcn_rsqf(x);
-      zr = fmaf(spec * p.flux, q * q * q, zr);
-      const int ix = (int)rint(__dmul_rn(u, p.theta));
-      const int iy = (int)rint(__dmul_rn(v, p.theta));
-      const unsigned ox = (unsigned)(ix + g.half), oy = (unsigned)(iy + g.half);
-      const bool inb = ox < (unsigned)g.side && oy < (unsigned)g.side;
-      const int key = inb ? (int)(oy * (unsigned)g.side + ox) : -1;
-      if (key != cur.key) {
-        if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
-        if (!inb && active) atomicOr(a.err, 1u);
-        cur.key = key;
-        cur.n = 0u;
-        cur.w = cur.zr = cur.zi = 0.0;
-      }
-      const double wd = (double)ww;
-      cur.n += 1u;
-      cur.w += wd;
-      cur.zr = fma(wd, (double)zr, cur.zr);
-      cur.zi = fma(wd, (double)zi, cur.zi);
+      for (int t = 0; t < G; ++t) {
+        if (jl + t >= len) break;                                   // uniform
+        if (wwg[t] == 0u) continue;                                  // uniform: flagged or padding
+        const double u = gg[t].x, v = gg[t].y, ww = __longlong_as_double((long long)wwg[t]);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
+          const float tt = (float)(ph - rint(ph));                   // turns, |t| <= 1/2
+          const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
+          float zr = fmaf(rg[t].x, cs, rg[t].y * sn);
+          const float zi = fmaf(rg[t].y, cs, -(rg[t].x * sn));
+          const float x = fmaf(p[i].q11, qg[t].x, fmaf(p[i].q12x2, qg[t].y, fmaf(p[i].q22, qg[t].z, 1.0f)));
+          const float q = __builtin_amdgcn_rsqf(x);
+          zr = fmaf(qg[t].w * p[i].flux, q * q * q, zr);
+          step(L[i], acc, a.err, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
+               (double)zr, (double)zi);
+        }
       }
     }
   }
-  if (cur.key >= 0 && active) flush(cnt, ws, zre, zim, g.base, cur);
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    if (L[i].key >= 0.0 && L[i].active) flush(acc, L[i]);
 }
 
 }  // namespace
 
-hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st) {
+hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st) {
+  const int ns = mixed ? kNsMixed : kNsF64;
+  ExtractArgs a = a0;
+  a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);
   const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
   const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
   const Sorted &v = a.sv;
+  const uint64_t *wt = reinterpret_cast<const uint64_t *>(v.wt);
   if (mixed)
-    hipLaunchKernelGGL(k_extract<true>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.u, v.v, v.w,
-                       reinterpret_cast<const uint32_t *>(v.chan), v.res, v.wt, a.chan->spec, a.acc.count, a.acc.wsum, a.acc.zre, a.acc.zim);
+    hipLaunchKernelGGL((k_extract<true, kNsMixed, kGroupMixed>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a,
+                       v.geo, v.quad, v.res, wt, a.acc.cell);
   else
-    hipLaunchKernelGGL(k_extract<false>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.u, v.v, v.w,
-                       reinterpret_cast<const uint32_t *>(v.chan), v.res, v.wt, a.chan->spec, a.acc.count, a.acc.wsum, a.acc.zre, a.acc.zim);
+    hipLaunchKernelGGL((k_extract<false, kNsF64, kGroupF64>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a,
+                       v.geo, v.quad, v.res, wt, a.acc.cell);
   return hipGetLastError();
 }
 

@@ -9,9 +9,10 @@
 // a uniform loop over the source's cells: each cell (uc, vc, W, W Re Vbar)
 // comes in through one scalar load shared by the wave.  Per (cell, point)
 // the quadratic form costs 7 ops and serves all knots; per (cell, point,
-// knot): 1 FMA, rsqrt, 2 MUL, 1 FMA, 1 MUL + 1 FMA.
-//   FP64 form:  v_rsq_f64 + one second-order refinement.
-//   Mixed form: FP32 cell data and arithmetic (v_rsq_f32), partial sums of
+// knot): 1 FMA, x^(-3/2), 1 FMA, 1 MUL + 1 FMA.
+//   FP64 form:  x^(-3/2) as v_rsq_f64 cubed with a first-order correction
+//               (5 ops, relative error < 3e-14), computed as (2/3) x^(-3/2).
+//   Mixed form: FP32 cell data and arithmetic (v_rsq_f32 cubed), partial sums of
 //               each block of kBlock cells folded into FP64 totals, so the
 //               FP32 rounding error grows with kBlock, not with the cell count.
 // The epilogue (logs, exps, log-sum-exp over knots) is FP64 in both forms.
@@ -23,6 +24,7 @@ namespace rlf {
 namespace {
 
 constexpr int kBlock = 32;
+constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
 
 // ln L(e) at valid grid point j (index into the valid-point list) of source s.
 template <int R, bool kExact, bool kMixed>
@@ -55,8 +57,7 @@ __device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int 
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         if (k < num_r) {
-          const double r = rsqrt_f64(fma(sk[k], q, 1.0));
-          const double f = r * r * r;
+          const double f = pow_m32_f64(fma(sk[k], q, 1.0));       // (2/3) f_c
           D[k] = fma(cl.w, f, D[k]);
           M[k] = fma(cl.z * f, f, M[k]);
         }
@@ -108,7 +109,9 @@ __device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int 
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     if (k < num_r) {
-      L[k] = D[k] * D[k] / (2.0 * M[k]) - 0.5 * log(M[k]);
+      // FP64 form: D and M carry (2/3) and (4/9) of their values; the ratio
+      // term is unchanged and ln M is off by ln(4/9) = -2 ln(3/2)
+      L[k] = D[k] * D[k] / (2.0 * M[k]) - 0.5 * log(M[k]) - (kMixed ? 0.0 : kLnPowM32Scale);
       mx = fmax(mx, L[k]);
     }
   }

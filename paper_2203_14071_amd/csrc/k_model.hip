@@ -5,8 +5,8 @@
 // record comes in through scalar loads shared by the wave.  Work per
 // (visibility, source) pair:
 //   FP64 form:  phase (3 FMA), exp(2 pi i phase) by exact reduction + LDS
-//               table + short polynomials (~19 ops), profile
-//               (3 FMA + rsqrt + 2 MUL), 2 FMA into the sum;
+//               table + short polynomials (~16 ops), profile
+//               (3 FMA + corrected rsqrt cube, 5 ops, + 2 MUL), 2 FMA into the sum;
 //   mixed form: phase and its reduction to [-1/2, 1/2] turns in FP64, then
 //               v_sin/v_cos (argument in turns), profile and sum in FP32.
 // Two entry kernels: visibilities in caller order (rlf_model_vis), and the
@@ -27,8 +27,7 @@ __device__ __forceinline__ double2 sum_f64(double u, double v, double w, const S
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
     const double2 cs = cis2pi_f64(ph, tab);
     const double x = fma(p.q11, uu, fma(p.q12x2, uv, fma(p.q22, vv, 1.0)));
-    const double r = rsqrt_f64(x);
-    const double amp = p.flux * (r * r * r);
+    const double amp = (kPowM32Scale * p.flux) * pow_m32_f64(x);
     ar = fma(amp, cs.x, ar);
     ai = fma(amp, cs.y, ai);
   }
@@ -118,25 +117,29 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.sv.n_vis) return;
   const int64_t i = a.sv.order[j];
+  const double4 g = a.sv.geo[j];
+  // The source loop comes before any store: loads that no store of this
+  // kernel can have clobbered stay scalar (one s_load per source per wave).
+  const double w = kMixed ? (double)reinterpret_cast<const float *>(a.weight)[i]
+                          : reinterpret_cast<const double *>(a.weight)[i];
   if (!kMixed) {
-    reinterpret_cast<double *>(a.sv.wt)[j] = reinterpret_cast<const double *>(a.weight)[i];
     double2 r = reinterpret_cast<const double2 *>(a.vis)[i];
     if (a.subtract) {
-      const double spec = a.chan->spec[a.n_chan > 1 ? a.sv.chan[j] : 0];
-      const double2 acc = sum_f64(a.sv.u[j], a.sv.v[j], a.sv.w[j], a.src, 0, a.n_src, tab);
-      r = make_double2(fma(-spec, acc.x, r.x), fma(-spec, acc.y, r.y));
+      const double2 acc = sum_f64(g.x, g.y, g.z, a.src, 0, a.n_src, tab);
+      r = make_double2(fma(-g.w, acc.x, r.x), fma(-g.w, acc.y, r.y));
     }
     reinterpret_cast<double2 *>(a.sv.res)[j] = r;
   } else {
-    reinterpret_cast<float *>(a.sv.wt)[j] = reinterpret_cast<const float *>(a.weight)[i];
     float2 r = reinterpret_cast<const float2 *>(a.vis)[i];
     if (a.subtract) {
-      const float spec = (float)a.chan->spec[a.n_chan > 1 ? a.sv.chan[j] : 0];
-      const float2 acc = sum_mixed(a.sv.u[j], a.sv.v[j], a.sv.w[j], a.src32, 0, a.n_src);
+      const float spec = (float)g.w;
+      const float2 acc = sum_mixed(g.x, g.y, g.z, a.src32, 0, a.n_src);
       r = make_float2(fmaf(-spec, acc.x, r.x), fmaf(-spec, acc.y, r.y));
     }
     reinterpret_cast<float2 *>(a.sv.res)[j] = r;
   }
+  // flagged weights (<= 0 or NaN) are stored as +0: the extraction tests bits
+  a.sv.wt[j] = w > 0.0 ? w : 0.0;
 }
 
 }  // namespace

@@ -46,17 +46,28 @@ __global__ __launch_bounds__(256) void k_uv_keys(SortKeyArgs a) {
   }
 }
 
+// Static per-visibility data in sorted order: coordinates in wavelengths
+// (exactly fl(u_m nu/c)), the channel's spectral factor, and the profile's
+// quadratic terms u^2, u v, v^2 (FP64, or FP32 from the FP32-rounded
+// coordinates for the mixed form), which are uniform across a wave in the
+// extraction and so are computed once here.
 __global__ __launch_bounds__(256) void k_sorted_static(Sorted sv, const double *u_m, const double *v_m,
-                                                       const double *w_m, int32_t n_chan, const ChanTable *chan) {
+                                                       const double *w_m, int32_t n_chan, const ChanTable *chan,
+                                                       int mixed) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sv.n_vis; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = sv.order[j];
     const int64_t row = i / n_chan;
     const int c = (int)(i - row * n_chan);
     const double sc = chan->scale[c];
-    sv.u[j] = __dmul_rn(u_m[row], sc);
-    sv.v[j] = __dmul_rn(v_m[row], sc);
-    sv.w[j] = __dmul_rn(w_m[row], sc);
-    sv.chan[j] = (uint8_t)c;
+    const double u = __dmul_rn(u_m[row], sc), v = __dmul_rn(v_m[row], sc);
+    const double spec = chan->spec[c];
+    sv.geo[j] = make_double4(u, v, __dmul_rn(w_m[row], sc), spec);
+    if (mixed) {
+      const float uf = (float)u, vf = (float)v;
+      reinterpret_cast<float4 *>(sv.quad)[j] = make_float4(uf * uf, uf * vf, vf * vf, (float)spec);
+    } else {
+      reinterpret_cast<double4 *>(sv.quad)[j] = make_double4(__dmul_rn(u, u), __dmul_rn(u, v), __dmul_rn(v, v), 0.0);
+    }
   }
 }
 
@@ -78,8 +89,9 @@ hipError_t sort_pairs_u32(void *tmp, size_t &tmp_bytes, const uint32_t *kin, uin
 }
 
 hipError_t launch_sorted_static(const Sorted &sv, const double *u_m, const double *v_m, const double *w_m,
-                                int32_t n_chan, const ChanTable *chan, hipStream_t st) {
-  hipLaunchKernelGGL(k_sorted_static, dim3(grid_for(sv.n_vis)), dim3(256), 0, st, sv, u_m, v_m, w_m, n_chan, chan);
+                                int32_t n_chan, const ChanTable *chan, int mixed, hipStream_t st) {
+  hipLaunchKernelGGL(k_sorted_static, dim3(grid_for(sv.n_vis)), dim3(256), 0, st, sv, u_m, v_m, w_m, n_chan, chan,
+                     mixed);
   return hipGetLastError();
 }
 

@@ -241,18 +241,13 @@ void free_facets(rlf_facets *f) {
   dfree(f->d_src);
   dfree(f->d_src32);
   dfree(f->sv.order);
-  dfree(f->sv.u);
-  dfree(f->sv.v);
-  dfree(f->sv.w);
-  dfree(f->sv.chan);
+  dfree(f->sv.geo);
+  dfree(f->sv.wt);
+  if (f->sv.quad) (void)hipFree(f->sv.quad);
   if (f->sv.res) (void)hipFree(f->sv.res);
-  if (f->sv.wt) (void)hipFree(f->sv.wt);
-  f->sv.res = f->sv.wt = nullptr;
+  f->sv.res = f->sv.quad = nullptr;
   dfree(f->d_geom);
-  dfree(f->acc.count);
-  dfree(f->acc.wsum);
-  dfree(f->acc.zre);
-  dfree(f->acc.zim);
+  dfree(f->acc.cell);
   dfree(f->cells.offsets);
   dfree(f->cells.n_nonempty);
   dfree(f->cells.ix);
@@ -290,18 +285,14 @@ int build_sorted(rlf_ctx *c, const rlf_obs *obs, const double mx[2], rlf_facets 
   // with zero weight (skipped) and zero coordinates in the padding
   const int64_t np = n + kSortedPad;
   if (int e = dalloc(c, &sv.order, n)) return e;
-  if (int e = dalloc(c, &sv.u, np)) return e;
-  if (int e = dalloc(c, &sv.v, np)) return e;
-  if (int e = dalloc(c, &sv.w, np)) return e;
-  if (int e = dalloc(c, &sv.chan, np)) return e;
+  if (int e = dalloc(c, &sv.geo, np)) return e;
+  if (int e = dalloc(c, &sv.wt, np)) return e;
+  HIPCHK(c, hipMalloc(&sv.quad, 4 * esz * (size_t)np));
   HIPCHK(c, hipMalloc(&sv.res, 2 * esz * (size_t)np));
-  HIPCHK(c, hipMalloc(&sv.wt, esz * (size_t)np));
-  HIPCHK(c, hipMemset(sv.u, 0, sizeof(double) * (size_t)np));
-  HIPCHK(c, hipMemset(sv.v, 0, sizeof(double) * (size_t)np));
-  HIPCHK(c, hipMemset(sv.w, 0, sizeof(double) * (size_t)np));
-  HIPCHK(c, hipMemset(sv.chan, 0, (size_t)np));
+  HIPCHK(c, hipMemset(sv.geo, 0, sizeof(double4) * (size_t)np));
+  HIPCHK(c, hipMemset(sv.wt, 0, sizeof(double) * (size_t)np));
+  HIPCHK(c, hipMemset(sv.quad, 0, 4 * esz * (size_t)np));
   HIPCHK(c, hipMemset(sv.res, 0, 2 * esz * (size_t)np));
-  HIPCHK(c, hipMemset(sv.wt, 0, esz * (size_t)np));
   double smax = 0.0;
   for (int k = 0; k < obs->n_chan; ++k) smax = std::fmax(smax, obs->freq_hz_host[k] / kC);
   const double su = mx[0] * smax, svv = mx[1] * smax;
@@ -327,7 +318,8 @@ int build_sorted(rlf_ctx *c, const rlf_obs *obs, const double mx[2], rlf_facets 
     if (e == hipSuccess) e = sort_pairs_u32(nullptr, tmp_bytes, kin, kout, vin, sv.order, n, c->stream);
     if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1);
     if (e == hipSuccess) e = sort_pairs_u32(tmp, tmp_bytes, kin, kout, vin, sv.order, n, c->stream);
-    if (e == hipSuccess) e = launch_sorted_static(sv, obs->u_m, obs->v_m, obs->w_m, obs->n_chan, c->d_chan, c->stream);
+    if (e == hipSuccess)
+      e = launch_sorted_static(sv, obs->u_m, obs->v_m, obs->w_m, obs->n_chan, c->d_chan, f->mixed, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = hip_fail(c, e, "uv sort of the visibilities");
   } while (0);
@@ -574,10 +566,7 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
     if ((rc = dalloc(c, &f->d_src, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_src32, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_geom, f->n_src))) break;
-    if ((rc = dalloc(c, &f->acc.count, total))) break;
-    if ((rc = dalloc(c, &f->acc.wsum, total))) break;
-    if ((rc = dalloc(c, &f->acc.zre, total))) break;
-    if ((rc = dalloc(c, &f->acc.zim, total))) break;
+    if ((rc = dalloc(c, &f->acc.cell, total))) break;
     if ((rc = dalloc(c, &f->cells.offsets, f->n_src + 1))) break;
     if ((rc = dalloc(c, &f->cells.n_nonempty, f->n_src))) break;
     if ((rc = dalloc(c, &f->cells.ix, total))) break;
@@ -603,10 +592,7 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpy(f->d_geom, f->geom.data(), sizeof(SrcGeom) * f->geom.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(f->acc.count, 0, sizeof(uint32_t) * (size_t)total);
-  if (e == hipSuccess) e = hipMemset(f->acc.wsum, 0, sizeof(double) * (size_t)total);
-  if (e == hipSuccess) e = hipMemset(f->acc.zre, 0, sizeof(double) * (size_t)total);
-  if (e == hipSuccess) e = hipMemset(f->acc.zim, 0, sizeof(double) * (size_t)total);
+  if (e == hipSuccess) e = hipMemset(f->acc.cell, 0, sizeof(double4) * (size_t)total);
   if (e == hipSuccess) e = hipMemset(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1));
   if (e == hipSuccess) e = hipMemset(f->d_redo, 0, sizeof(int32_t) * (size_t)f->n_src);
   if (e == hipSuccess) e = hipDeviceSynchronize();

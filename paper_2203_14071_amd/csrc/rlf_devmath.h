@@ -3,23 +3,27 @@
 // cis2pi_f64: exp(2 pi i phi) in FP64 for phase arguments of thousands of
 // turns.  Reduction is exact: r = phi - rint(phi) in [-1/2, 1/2] (the
 // difference is a multiple of ulp(phi) no larger than 1/2, so it is
-// representable), k = rint(256 r), d = r - k/256 in [-1/512, 1/512] (again
-// exact).  exp(2 pi i r) = T[k] * exp(2 pi i d) with T[k] = exp(2 pi i k/256)
-// from a 257-entry table in LDS, and exp(i x), |x| <= pi/256 < 0.0123, from
-// its Taylor series: cos to x^6 (truncation < x^8/8! < 6e-21) and sin to x^7
-// (truncation < x^9/9! < 2e-23).  About 19 VALU operations against ~40 for a
-// general-range sincospi.
+// representable), k = rint(1024 r), d = r - k/1024 in [-1/2048, 1/2048]
+// (again exact).  exp(2 pi i r) = T[k] * exp(2 pi i d) with
+// T[k] = exp(2 pi i k/1024) from a 1025-entry table in LDS (16.4 KB), and
+// exp(i x), |x| <= pi/1024 < 3.1e-3, from its Taylor series: cos to x^4
+// (truncation < x^6/6! < 1.2e-18) and sin to x^5 (truncation
+// < x^7/7! < 4.3e-22).  About 16 VALU operations.
 //
-// rsqrt_f64: v_rsq_f64 refined by one second-order step,
-// y = y0 (1 + e/2 + 3 e^2 / 8) with e = 1 - x y0^2; arguments here are finite
-// and >= 1, so no special-case handling is needed.
+// pow_m32_f64: (2/3) x^(-3/2) for x >= 1 from v_rsq_f64 (relative error
+// ~2^-24) with one correction: with y = rsq(x), x^(-3/2) = y^3 (1 + 3e/2 +
+// O(e^2)) where e = 1 - x y^2, and y^3 (1 + 3e/2) = (3/2) y^3 (5/3 - x y^2).
+// The returned y^3 (5/3 - x y^2) has relative error ~ (15/8) e^2 < 3e-14;
+// five VALU operations.  The constant 2/3 is left to the callers (it
+// multiplies every profile value: a flux scale, or a constant offset of the
+// log-likelihood).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace rlf {
 
-constexpr int kCisTable = 256;                  // table steps per turn
+constexpr int kCisTable = 1024;                 // table steps per turn
 
 // Fill the block's LDS table (257 entries, k = -128..128).  Call from every
 // thread of the block, followed by __syncthreads().
@@ -38,18 +42,21 @@ __device__ __forceinline__ double2 cis2pi_f64(double phi, const double2 *tab) {
   const double d = fma(kf, -1.0 / kCisTable, r);
   const double x = d * 6.283185307179586476925286766559;   // 2 pi
   const double x2 = x * x;
-  // cos x = 1 - x^2/2 + x^4/24 - x^6/720
-  const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-  // sin x = x (1 - x^2/6 + x^4/120 - x^6/5040)
-  const double sx = x * fma(x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+  // cos x = 1 - x^2/2 + x^4/24;  sin x = x (1 - x^2/6 + x^4/120)
+  const double cx = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0);
+  const double sx = x * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
   const double2 t = tab[(int)kf + kCisTable / 2];
   return make_double2(fma(t.x, cx, -(t.y * sx)), fma(t.x, sx, t.y * cx));
 }
 
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  const double y0 = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * y0, y0, 1.0);
-  return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+// (2/3) x^(-3/2), x >= 1 and finite.
+__device__ __forceinline__ double pow_m32_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double y2 = y * y;
+  const double h = fma(-x, y2, 5.0 / 3.0);
+  return (y2 * y) * h;
 }
+
+constexpr double kPowM32Scale = 1.5;              // x^(-3/2) = kPowM32Scale * pow_m32_f64(x)
 
 }  // namespace rlf

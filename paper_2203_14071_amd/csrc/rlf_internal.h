@@ -46,8 +46,7 @@ struct ChanTable {
 
 // Dense accumulators of one extraction.
 struct DenseAcc {
-  uint32_t *count;
-  double *wsum, *zre, *zim;
+  double4 *cell;             // per dense cell: (W, Z re, Z im, count) -- one address per run flush
 };
 
 // Compacted facets (CSR by source, cells sorted by (iy, ix)).
@@ -79,10 +78,10 @@ struct ModelArgs {
 struct Sorted {
   int64_t n_vis;
   uint32_t *order;           // sorted position -> visibility index row*n_chan + chan
-  double *u, *v, *w;         // wavelengths
-  uint8_t *chan;             // channel of each sorted visibility
+  double4 *geo;              // (u, v, w) in wavelengths, spectral factor (nu_c/nu_ref)^beta
+  void *quad;                // (u^2, u v, v^2, _) double4 | (same in FP32 from (float)u, (float)v, spec) float4
   void *res;                 // residual, complex128 | complex64
-  void *wt;                  // weight, f64 | f32
+  double *wt;                // weight, 0 where w <= 0 or NaN (flagged)
 };
 
 struct SortKeyArgs {
@@ -213,7 +212,7 @@ hipError_t launch_sort_keys(const SortKeyArgs &a, hipStream_t st);
 hipError_t sort_pairs_u32(void *tmp, size_t &tmp_bytes, const uint32_t *kin, uint32_t *kout, const uint32_t *vin,
                           uint32_t *vout, int64_t n, hipStream_t st);
 hipError_t launch_sorted_static(const Sorted &sv, const double *u_m, const double *v_m, const double *w_m,
-                                int32_t n_chan, const ChanTable *chan, hipStream_t st);
+                                int32_t n_chan, const ChanTable *chan, int mixed, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, int mixed, hipStream_t st);
 hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st);
 hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st);

@@ -48,7 +48,26 @@ MODEL_FLOP_PAIR = 19
 # HBM bytes per launch of the dominant kernel (extraction) at this workload,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by a plain copy's
 # reading), for the kernel as it is now; None where not measured.
-EXTRACT_TRAFFIC_BYTES = {"fp64": None, "mixed": None}
+# (profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md: fetch 1633.6 / 1219.1 MB,
+# write 6046.6 MB, nearly all of it the memory-side run-flush atomics)
+EXTRACT_TRAFFIC_BYTES = {"fp64": 7680.2e6, "mixed": 7265.7e6}
+# VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
+# Slots per unit of work count the method's necessary operations at their
+# measured gfx950 cost (FP64 and FP32 add/mul/FMA/round 1, v_sin/v_cos/v_rsq
+# FP32 2, v_rsq FP64 4):
+#   extraction FP64 46 = phase 3, reduction + table sincos 15, rotation 4,
+#     profile (quadratic form 3, rsq 4 + correction 4, spec S 2) 13, index 6,
+#     run compare 1, accumulate 4;   mixed 36 = phase 3, reduction 3,
+#     sin + cos 4, rotation 4, profile 9, index 6, compare 1, accumulate 6
+#   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
+#     D 1, Mm 2;  mixed 8 = x 1, rsq 2, cube 2, D 1, Mm 2; plus 5 per
+#     (cell, point) shared by the knots
+#   sky-model DFT FP64 32 = phase 3, reduction + sincos 15, profile 3 + 8,
+#     amplitude 1, accumulate 2;  mixed 20 = phase 3, reduction 3, sin + cos 4,
+#     profile 3 + rsq 2 + cube 2, amplitude 1, accumulate 2
+SLOT_PEAK = 256 * 64 * 2.4e9
+SLOTS = {"fp64": {"extract": 46, "fit_knot": 12, "fit_point": 5, "model": 32},
+         "mixed": {"extract": 36, "fit_knot": 8, "fit_point": 5, "model": 20}}
 
 
 def log(*a):
@@ -85,9 +104,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="sources in the oracle baseline sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="sources in the oracle baseline sample (0 = skip)")
     ap.add_argument("--only", action="store_true", help="time only the --precision form (for profiling)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the config-3 batched / surrogate block")
+    ap.add_argument("--only-config3", action="store_true",
+                    help="run only the config-3 block (with --populations none: no network, for profiling)")
     ap.add_argument("--train-sources", type=int, default=200_000)
     ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--nsigma", default="3,4", help="window half-widths (in predicted sigmas) to compare")
@@ -117,6 +138,12 @@ def main():
 
     import oracle  # only for the cpu_baseline leg and the oracle's parameter defaults
 
+    pops = [] if args.populations in ("", "none") else args.populations.split(",")
+    if args.only_config3:
+        print(json.dumps(run_surrogate(max(3, args.steps // 3), args.train_sources, args.epochs,
+                                       [float(v) for v in args.nsigma.split(",")], pops, args.check_stride,
+                                       args.full_frac)), flush=True)
+        return
     main_form = run_form(args.precision, args.steps, args.warmup)
     res = main_form["json"]
     if args.only:
@@ -131,13 +158,14 @@ def main():
         "gvis_per_s_extract": other_form["json"]["gvis_per_s_extract"],
         "roofline": other_form["json"]["roofline"],
         "kernel_rooflines": other_form["json"]["kernel_rooflines"],
+        "slot_roofline_frac": other_form["json"]["slot_roofline_frac"],
         "max_abs_de_vs_" + args.precision: float(de),
         "note": "same synthetic field; the mixed form takes complex64 visibilities and f32 weights",
     }
     if not args.no_surrogate:
         res["batched_and_surrogate"] = run_surrogate(max(3, args.steps // 3), args.train_sources, args.epochs,
                                                      [float(v) for v in args.nsigma.split(",")],
-                                                     args.populations.split(","), args.check_stride,
+                                                     pops, args.check_stride,
                                                      args.full_frac)
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} sources")
@@ -371,6 +399,15 @@ def run_form(precision, steps, warmup):
         "model": roof("sky-model residual DFT (k_model)", MODEL_FLOP_PAIR * pairs, stage_ms[0],
                       f"{MODEL_FLOP_PAIR} FLOP per (visibility, source) pair x {pairs:.4g} pairs"),
     }
+    sl = SLOTS[precision]
+    fit_units = float(np.sum(cells)) * n_valid
+    slot_roofline = {
+        "peak_lane_slots_per_s": SLOT_PEAK,
+        "extract": round(sl["extract"] * pairs / (stage_ms[1] * 1e-3) / SLOT_PEAK, 4),
+        "fit": round((sl["fit_knot"] * p.num_r + sl["fit_point"]) * fit_units / (stage_ms[2] * 1e-3) / SLOT_PEAK, 4),
+        "model": round(sl["model"] * pairs / (stage_ms[0] * 1e-3) / SLOT_PEAK, 4),
+        "slots_per_unit": sl,
+    }
     dominant = max(("extract", "fit", "model"), key=lambda k: {"model": stage_ms[0], "extract": stage_ms[1],
                                                                "fit": stage_ms[2]}[k])
     roofline = dict(kernels[dominant])
@@ -406,6 +443,7 @@ def run_form(precision, steps, warmup):
                      "fit": round(stage_ms[2], 4)},
         "roofline": roofline,
         "kernel_rooflines": kernels,
+        "slot_roofline_frac": slot_roofline,
         "facet_cells": {"total": int(cells.sum()), "mean": round(float(cells.mean()), 1),
                         "min": int(cells.min()), "max": int(cells.max())},
         "fit_quality": {"rms_e_minus_true": round(rms, 5), "bad_var": int(np.sum(flags & 1)),

@@ -34,3 +34,4 @@ from .likelihood import (alpha_knots, spline_quadrature_weights, log_normal_prio
                          e_grid, loglike_alpha, marginal_surface, log_alpha_weights)
 from .estimate import Estimate, estimate, FLAG_BAD_VAR, FLAG_EMPTY, FLAG_EDGE, FLAG_FALLBACK
 from .fit import Params, fit_source, fit_sources, narrowed_fit, window_rejected
+from .sequential import FLAG_REFIT, SkyCatalogue, fit_sequential

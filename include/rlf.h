@@ -62,7 +62,8 @@ enum {
   RLF_FLAG_BAD_VAR = 1,   /* sigma(e1) or sigma(e2) <= bad_sigma, or sqrt(det C) <= bad_sqrtdet (Sec. 4.1) */
   RLF_FLAG_EMPTY = 2,     /* facet holds no visibility with positive weight; outputs are NaN               */
   RLF_FLAG_EDGE = 4,      /* maximum on the edge of the evaluated ellipticity region                       */
-  RLF_FLAG_FALLBACK = 8   /* narrowed grid rejected; the full grid was evaluated instead                   */
+  RLF_FLAG_FALLBACK = 8,  /* narrowed grid rejected; the full grid was evaluated instead                   */
+  RLF_FLAG_REFIT = 16     /* rlf_fit_sequential: fitted again at the end against the final sky model         */
 };
 
 /* rlf_model_vis modes. */
@@ -249,6 +250,30 @@ typedef struct {
  * and the flags. */
 int rlf_fit_sources(rlf_ctx *ctx, const rlf_facets *facets, const rlf_fit_opts *opts,
                     rlf_fit_out *out);
+
+/* Sequential sky-model refinement (Sec. 2.1, 2.3, 2.4 and the chunked form
+ * of Sec. 3.1).  Sources are taken in catalogue order (decreasing flux) in
+ * chunks of `chunk`; the sky model starts from the catalogue's shapes (e1, e2;
+ * circular at the start of the paper's procedure).  Each chunk's sources are
+ * extracted from obs->vis minus the current sky model (their own current
+ * model restored) and fitted on the full grid; every chunk source whose fit
+ * has neither RLF_FLAG_BAD_VAR nor RLF_FLAG_EMPTY then takes its measured
+ * (e1, e2) into the sky model before the next chunk.  With refit_bad
+ * nonzero, the sources flagged RLF_FLAG_BAD_VAR are extracted and fitted once
+ * more at the end against the final sky model (flag RLF_FLAG_REFIT added),
+ * and a finite refit also enters the final shapes.  chunk = 1 is the paper's
+ * serial order, chunk = n_src with refit_bad = 0 equals rlf_facets_create +
+ * rlf_extract_facets + rlf_fit_sources.
+ *   out      device [n_src] final estimate of every source (flags required,
+ *            surface ignored)
+ *   e1_host, e2_host   host [n_src] final sky-model shapes
+ * The residual is kept in a library-allocated device buffer the size of
+ * obs->vis and updated in place (R += old models, R -= new models of the
+ * refined sources); obs->vis is not modified.  Synchronises after every
+ * chunk (the host decides which shapes enter the model).  RLF_EINVAL for
+ * chunk < 1 or a NULL argument. */
+int rlf_fit_sequential(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat, int64_t chunk, int32_t refit_bad,
+                       const rlf_fit_out *out, double *e1_host, double *e2_host);
 
 /* Batched pass over every source (Sec. 2.2-2.4 in one unit): the residual of
  * this catalogue's sky model (as rlf_extract_facets with residual = NULL),

@@ -31,6 +31,19 @@ __global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n, double v
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// dst[idx[i]] = src[i] (| bits for the 32-bit form), i < n; idx in range by
+// construction of the caller.
+__global__ __launch_bounds__(256) void k_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[idx[i]] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t bits,
+                                                     uint32_t *dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[idx[i]] = src[i] | bits;
+}
+
 unsigned grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
@@ -40,6 +53,19 @@ unsigned grid_for(int64_t n) {
 
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st) {
   hipLaunchKernelGGL(k_absmax, dim3(grid_for(n)), dim3(256), 0, st, x, n, out2, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_f64, dim3(grid_for(n)), dim3(256), 0, st, src, idx, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t bits, uint32_t *dst,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_u32, dim3(grid_for(n)), dim3(256), 0, st, src, idx, n, bits, dst);
   return hipGetLastError();
 }
 

@@ -240,12 +240,14 @@ int set_device(rlf_ctx *c) {
 void free_facets(rlf_facets *f) {
   dfree(f->d_src);
   dfree(f->d_src32);
-  dfree(f->sv.order);
-  dfree(f->sv.geo);
-  dfree(f->sv.wt);
-  if (f->sv.quad) (void)hipFree(f->sv.quad);
-  if (f->sv.res) (void)hipFree(f->sv.res);
-  f->sv.res = f->sv.quad = nullptr;
+  if (f->owns_sorted) {
+    dfree(f->sv.order);
+    dfree(f->sv.geo);
+    dfree(f->sv.wt);
+    if (f->sv.quad) (void)hipFree(f->sv.quad);
+    if (f->sv.res) (void)hipFree(f->sv.res);
+  }
+  f->sv = Sorted{};
   dfree(f->d_geom);
   dfree(f->acc.cell);
   dfree(f->cells.offsets);
@@ -499,25 +501,37 @@ int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_
   return RLF_OK;
 }
 
-int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets **out) {
-  if (!c) return RLF_EINVAL;
-  c->err.clear();
+}  // extern "C"
+
+namespace rlf {
+
+// A facet object for `cat`; with `share`, the uv-sorted layout of `share`
+// (made for the same observation) is borrowed instead of sorted again.
+int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const rlf_facets *share,
+                  rlf_facets **out) {
   if (!out) return fail(c, RLF_EINVAL, "out is NULL");
   if (int e = check_obs(c, obs)) return e;
   if (int e = check_cat(c, cat, true)) return e;
   if (int e = set_device(c)) return e;
-  // largest |u|, |v| (metres) bound every cell index
-  HIPCHK(c, hipMemsetAsync(c->d_absmax, 0, 2 * sizeof(double), c->stream));
-  HIPCHK(c, launch_absmax(obs->u_m, obs->n_rows, c->d_absmax, 0, c->stream));
-  HIPCHK(c, launch_absmax(obs->v_m, obs->n_rows, c->d_absmax, 1, c->stream));
   double mx[2] = {0.0, 0.0};
-  HIPCHK(c, hipMemcpyAsync(mx, c->d_absmax, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (!is_fin(mx[0]) || !is_fin(mx[1])) return fail(c, RLF_EINVAL, "obs: non-finite u or v");
+  if (share) {
+    mx[0] = share->mx[0];
+    mx[1] = share->mx[1];
+  } else {
+    // largest |u|, |v| (metres) bound every cell index
+    HIPCHK(c, hipMemsetAsync(c->d_absmax, 0, 2 * sizeof(double), c->stream));
+    HIPCHK(c, launch_absmax(obs->u_m, obs->n_rows, c->d_absmax, 0, c->stream));
+    HIPCHK(c, launch_absmax(obs->v_m, obs->n_rows, c->d_absmax, 1, c->stream));
+    HIPCHK(c, hipMemcpyAsync(mx, c->d_absmax, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!is_fin(mx[0]) || !is_fin(mx[1])) return fail(c, RLF_EINVAL, "obs: non-finite u or v");
+  }
 
   rlf_facets *f = new (std::nothrow) rlf_facets();
   if (!f) return fail(c, RLF_ENOMEM, "host allocation");
   f->ctx = c;
+  f->mx[0] = mx[0];
+  f->mx[1] = mx[1];
   f->n_src = cat->n_src;
   f->mixed = c->p.precision == RLF_MIXED;
   {
@@ -607,13 +621,31 @@ int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rl
     return r;
   }
   f->model_key = cat_key(cat);
-  if (int r = build_sorted(c, obs, mx, f)) {
+  if (share) {
+    if (int e = chan_table(c, obs)) {
+      free_facets(f);
+      delete f;
+      return e;
+    }
+    f->sv = share->sv;
+    f->owns_sorted = false;
+  } else if (int r = build_sorted(c, obs, mx, f)) {
     free_facets(f);
     delete f;
     return r;
   }
   *out = f;
   return RLF_OK;
+}
+
+}  // namespace rlf
+
+extern "C" {
+
+int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets **out) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  return create_facets(c, obs, cat, nullptr, out);
 }
 
 int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *residual,

@@ -220,6 +220,9 @@ hipError_t launch_fit_queue(const FitArgs &a, const QueueArgs &q, int mixed, int
 int fit_queue_blocks_per_cu(int mixed, int num_r);
 hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
+hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t st);
+hipError_t launch_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t bits, uint32_t *dst,
+                              hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs &g, int split_k, hipStream_t st);

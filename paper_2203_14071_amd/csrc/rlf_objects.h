@@ -46,6 +46,8 @@ struct rlf_facets {
   int64_t dense_total = 0;
   int mixed = 0;
   double spec_norm = 1.0;                    // mean spectral factor over the channels
+  double mx[2] = {0.0, 0.0};                 // largest |u_m|, |v_m| of the observation
+  bool owns_sorted = true;                   // false: sv borrowed from another facet object
   std::vector<double> alpha;                 // catalogue sizes at creation
   std::vector<double> theta;
   std::vector<double> model_key;             // shapes of the uploaded model table
@@ -65,6 +67,8 @@ struct rlf_facets {
 namespace rlf {
 
 int fail(rlf_ctx *c, int code, const std::string &msg);
+int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const rlf_facets *share,
+                  rlf_facets **out);
 int hip_fail(rlf_ctx *c, hipError_t e, const char *what);
 
 #define HIPCHK(ctx, call)                                    \

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librlf.so")
 
 RLF_OK, RLF_EINVAL, RLF_ENOMEM, RLF_EDEVICE, RLF_ERANGE, RLF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RLF_FP64, RLF_MIXED = 0, 1
-RLF_FLAG_BAD_VAR, RLF_FLAG_EMPTY, RLF_FLAG_EDGE, RLF_FLAG_FALLBACK = 1, 2, 4, 8
+RLF_FLAG_BAD_VAR, RLF_FLAG_EMPTY, RLF_FLAG_EDGE, RLF_FLAG_FALLBACK, RLF_FLAG_REFIT = 1, 2, 4, 8, 16
 RLF_MODEL_WRITE, RLF_MODEL_ACCUMULATE, RLF_MODEL_RESIDUAL = 0, 1, 2
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -80,6 +80,8 @@ _SIGNATURES = {
     "rlf_pass_create": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), _c_vp,
                          ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out), ctypes.c_char_p,
                          ctypes.POINTER(_c_vp)], ctypes.c_int),
+    "rlf_fit_sequential": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), ctypes.c_int64,
+                            ctypes.c_int32, ctypes.POINTER(rlf_fit_out), _c_dp, _c_dp], ctypes.c_int),
     "rlf_pass_launch": ([_c_vp], ctypes.c_int),
     "rlf_pass_tiles": ([_c_vp, _c_ip, _c_ip], ctypes.c_int),
     "rlf_pass_free": ([_c_vp], ctypes.c_int),
@@ -238,6 +240,18 @@ class Context:
         flags (i32 viewed as u32), surface (f64) -- any may be absent except flags."""
         o, r = _fit_structs(out, mode, window, want_surface, fallback, check_stride)
         return self._check(lib().rlf_fit_sources(self.h, facets.h, ctypes.byref(o), ctypes.byref(r)))
+
+    def fit_sequential(self, obs: Obs, cat, chunk, out: dict, refit_bad=True, prior_mu=None):
+        """Sequential sky-model refinement; `out` as for fit_sources (e1, e2,
+        flags required).  Returns the final model shapes (e1, e2) as numpy."""
+        o = obs.c()
+        c, keep = catalog(cat, prior_mu)
+        _, r = _fit_structs(out, 0, None, False, False)
+        e1 = np.zeros(c.n_src)
+        e2 = np.zeros(c.n_src)
+        self._check(lib().rlf_fit_sequential(self.h, ctypes.byref(o), ctypes.byref(c), int(chunk),
+                                             1 if refit_bad else 0, ctypes.byref(r), _dp(e1), _dp(e2)))
+        return e1, e2
 
     def pass_create(self, obs: Obs, cat, facets: "Facets", out: dict, tune_path=None, mode=0, window=None,
                     want_surface=False, fallback=False, prior_mu=None, check_stride=0) -> "Pass":

@@ -1,0 +1,94 @@
+"""Sequential sky-model refinement through the C ABI (rlf_fit_sequential)
+against the oracle's fit_sequential: chunks of 1, 3 and all sources, bad
+fits refitted at the end, on a crowded 8-source field where the refinement
+changes the faint sources' facets."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.sequential import FLAG_REFIT, SkyCatalogue, fit_sequential
+from paper_2203_14071_amd import rlf, synth
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+BAD_SIGMA = 0.14          # flags about half of this field's fits, so the refit runs
+
+
+def _field():
+    cfg = dataclasses.replace(synth.small_config(0, n_ant=12, n_time=20, n_src=8), field_deg=0.05)
+    o = synth.observation(0, cfg)
+    cat = synth.catalogue(cfg, np.random.default_rng(21))
+    rng = np.random.default_rng(22)
+    vis = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat)
+    vis = vis + cfg.noise_sigma_jy * (rng.standard_normal(vis.size) + 1j * rng.standard_normal(vis.size))
+    return o, cat, vis
+
+
+@pytest.mark.parametrize("precision,chunk", [("fp64", 1), ("fp64", 3), ("fp64", 8), ("mixed", 3)])
+def test_sequential_matches_oracle(precision, chunk):
+    o, cat, vis = _field()
+    mixed = precision == "mixed"
+    n = cat.n_src
+    start = SkyCatalogue(cat.l, cat.m, cat.flux_jy, cat.alpha_arcsec, np.zeros(n), np.zeros(n))
+    p = dataclasses.replace(oracle.Params(), bad_sigma=BAD_SIGMA)
+    ref, re1, re2 = fit_sequential(o, vis, start, chunk=chunk, refit_bad=True, p=p)
+    ctx = rlf.Context(0, None, rlf.params(bad_sigma=BAD_SIGMA, precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64))
+    data = vis.astype(np.complex64) if mixed else vis
+    obs = G.make_obs(o, data, mixed=mixed)
+    out = G.fit_out_tensors(n, surface=False)
+    e1, e2 = ctx.fit_sequential(obs, G.circular(cat), chunk, out, refit_bad=True)
+    h = G.host(out)
+    tol = 1e-4 if mixed else 1e-8
+    n_refit = 0
+    for s in range(n):
+        assert int(h["flags"][s]) == ref[s].flags, (s, int(h["flags"][s]), ref[s].flags)
+        n_refit += bool(ref[s].flags & FLAG_REFIT)
+        for k in ("e1", "e2", "s1", "s2"):
+            assert abs(h[k][s] - getattr(ref[s], k)) <= tol, (s, k, h[k][s], getattr(ref[s], k))
+        if not mixed:
+            assert int(h["argmax"][s]) == ref[s].argmax and int(h["n_above"][s]) == ref[s].n_above
+    assert 0 < n_refit < n
+    assert np.max(np.abs(e1 - re1)) <= tol and np.max(np.abs(e2 - re2)) <= tol
+    ctx.close()
+
+
+def test_one_chunk_without_refit_is_the_plain_pass():
+    o, cat, vis = _field()
+    n = cat.n_src
+    ctx = rlf.Context(0)
+    obs = G.make_obs(o, vis)
+    catc = G.circular(cat)
+    out = G.fit_out_tensors(n, surface=False)
+    e1, e2 = ctx.fit_sequential(obs, catc, n, out, refit_bad=False)
+    torch = G.torch_cuda()
+    resid = torch.empty_like(obs.vis)
+    ctx.model_vis(obs, catc, resid, mode=rlf.RLF_MODEL_RESIDUAL)
+    f = ctx.facets_create(obs, catc)
+    ctx.extract_facets(obs, catc, resid, f)
+    plain = G.fit_out_tensors(n, surface=False)
+    ctx.fit_sources(f, plain)
+    a, b = G.host(out), G.host(plain)
+    assert np.array_equal(a["flags"], b["flags"]) and np.array_equal(a["argmax"], b["argmax"])
+    for k in ("e1", "e2", "s1", "s2", "c12"):
+        assert np.allclose(a[k], b[k], rtol=0, atol=1e-10), k
+    good = (b["flags"] & (rlf.RLF_FLAG_BAD_VAR | rlf.RLF_FLAG_EMPTY)) == 0
+    assert np.array_equal(e1[good], b["e1"][good]) and np.all(e1[~good] == 0.0)
+    f.free()
+    ctx.close()
+
+
+def test_sequential_argument_errors():
+    o, cat, vis = _field()
+    ctx = rlf.Context(0)
+    obs = G.make_obs(o, vis)
+    out = G.fit_out_tensors(cat.n_src, surface=False)
+    with pytest.raises(rlf.RlfError):
+        ctx.fit_sequential(obs, G.circular(cat), 0, out)
+    bad = dict(out)
+    bad.pop("e1")
+    with pytest.raises(rlf.RlfError):
+        ctx.fit_sequential(obs, G.circular(cat), 2, bad)
+    ctx.close()

@@ -35,3 +35,4 @@ from .likelihood import (alpha_knots, spline_quadrature_weights, log_normal_prio
 from .estimate import Estimate, estimate, FLAG_BAD_VAR, FLAG_EMPTY, FLAG_EDGE, FLAG_FALLBACK
 from .fit import Params, fit_source, fit_sources, narrowed_fit, window_rejected
 from .sequential import FLAG_REFIT, SkyCatalogue, fit_sequential
+from .refine import FLAG_REFINED, refine_source

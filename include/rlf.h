@@ -63,7 +63,8 @@ enum {
   RLF_FLAG_EMPTY = 2,     /* facet holds no visibility with positive weight; outputs are NaN               */
   RLF_FLAG_EDGE = 4,      /* maximum on the edge of the evaluated ellipticity region                       */
   RLF_FLAG_FALLBACK = 8,  /* narrowed grid rejected; the full grid was evaluated instead                   */
-  RLF_FLAG_REFIT = 16     /* rlf_fit_sequential: fitted again at the end against the final sky model         */
+  RLF_FLAG_REFIT = 16,    /* rlf_fit_sequential: fitted again at the end against the final sky model         */
+  RLF_FLAG_REFINED = 32   /* rlf_refine_sources: the estimate comes from a finer local grid                  */
 };
 
 /* rlf_model_vis modes. */
@@ -250,6 +251,24 @@ typedef struct {
  * and the flags. */
 int rlf_fit_sources(rlf_ctx *ctx, const rlf_facets *facets, const rlf_fit_opts *opts,
                     rlf_fit_out *out);
+
+/* Adaptive refinement of the estimates of the last full-grid rlf_fit_sources
+ * call on `facets` (Sec. 2.4: the likelihood is sampled around its maximum
+ * until NP_MAX samples lie above the threshold or the resolution E_RES is
+ * reached).  Nested grids: level L has the points e = k * e_step / 2^L, k
+ * integer, |e| < 1 tested on the integers; level 0 is the fit's grid.  A
+ * source whose thresholded set at level L - 1 holds fewer than np_max points
+ * is evaluated at level L on that set's bounding box widened by one level
+ * L - 1 step (at most 64 points per axis, else 64 centred on the maximum);
+ * the last level is the first with step <= e_res.  Refined sources get the
+ * thresholded likelihood-weighted moments of their last window in out (e1,
+ * e2, s1, s2, c12, lmax, n_above; argmax keeps the full-grid index), the
+ * bad-variance flag re-evaluated with the refined widths, and
+ * RLF_FLAG_REFINED; other sources and empty facets are untouched.  `out`
+ * holds the full-grid results on entry (flags required).  The paper's
+ * values: np_max = 30, e_res = 0.003 (three levels from the 0.02 grid).
+ * RLF_EINVAL for np_max < 1 or e_res <= 0 or below e_step / 4096. */
+int rlf_refine_sources(rlf_ctx *ctx, rlf_facets *facets, int32_t np_max, double e_res, rlf_fit_out *out);
 
 /* Sequential sky-model refinement (Sec. 2.1, 2.3, 2.4 and the chunked form
  * of Sec. 3.1).  Sources are taken in catalogue order (decreasing flux) in

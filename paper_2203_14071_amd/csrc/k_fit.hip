@@ -27,15 +27,10 @@ constexpr int kBlock = 32;
 constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
 
 // ln L(e) at valid grid point j (index into the valid-point list) of source s.
+// ln L(e) of source s at (e1, e2), |e| < 1; NaN for an empty facet.
 template <int R, bool kExact, bool kMixed>
-__device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int s, int j) {
+__device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int s, double e1, double e2) {
   const int num_r = kExact ? R : num_r_arg;
-  double *out = a.lsurf + (int64_t)s * a.n_valid + j;
-  const int idx = a.epts[j];
-  const int i1 = idx / a.n_e, i2 = idx - (idx / a.n_e) * a.n_e;
-  const int ctr = (a.n_e - 1) / 2;
-  const double e1 = (double)(i1 - ctr) * a.e_step;
-  const double e2 = (double)(i2 - ctr) * a.e_step;
   const double det = 1.0 - e1 * e1 - e2 * e2;
   const double g = 1.0 / (det * det);
   const int64_t c0 = a.offsets[s], c1 = a.offsets[s + 1];
@@ -99,10 +94,7 @@ __device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int 
     for (; cb + kBlock <= c1; cb += kBlock) block(cb, kBlock);
     if (cb < c1) block(cb, (int)(c1 - cb));
   }
-  if (c1 == c0) {
-    *out = NAN;
-    return;
-  }
+  if (c1 == c0) return NAN;
   const double *lw = a.logw + (int64_t)s * a.num_r;
   double L[R];
   double mx = -INFINITY;
@@ -119,7 +111,39 @@ __device__ __forceinline__ void eval_point(const FitArgs &a, int num_r_arg, int 
 #pragma unroll
   for (int k = 0; k < R; ++k)
     if (k < num_r) acc += exp(lw[k] + L[k] - mx);
-  *out = mx + log(acc);
+  return mx + log(acc);
+}
+
+// ln L(e) at valid grid point j (index into the valid-point list) of source s.
+template <int R, bool kExact, bool kMixed>
+__device__ __forceinline__ void eval_point(const FitArgs &a, int num_r, int s, int j) {
+  const int idx = a.epts[j];
+  const int i1 = idx / a.n_e, i2 = idx - (idx / a.n_e) * a.n_e;
+  const int ctr = (a.n_e - 1) / 2;
+  a.lsurf[(int64_t)s * a.n_valid + j] =
+      loglike_e<R, kExact, kMixed>(a, num_r, s, (double)(i1 - ctr) * a.e_step, (double)(i2 - ctr) * a.e_step);
+}
+
+// Refinement level: one thread per point of the source's window at
+// resolution e_step / 2^level, e = k * that step, |e| < 1 tested on the
+// integers; -inf outside the domain.
+template <int R, bool kExact, bool kMixed>
+__global__ __launch_bounds__(256) void k_refine_eval(FitArgs a, RefineArgs r, int num_r) {
+  const int s = blockIdx.y;
+  const int32_t *w = r.win + (int64_t)s * 5;
+  if (!w[0]) return;
+  const int n1 = w[3], n2 = w[4];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n1 * n2) return;
+  const int64_t k1 = w[1] + t / n2, k2 = w[2] + t % n2;
+  const int64_t lim = (int64_t)r.unit << r.level;
+  double *out = r.lloc + (int64_t)s * r.max_side * r.max_side + t;
+  if (k1 * k1 + k2 * k2 >= lim * lim) {
+    *out = -INFINITY;
+    return;
+  }
+  const double res = a.e_step / (double)(1 << r.level);
+  *out = loglike_e<R, kExact, kMixed>(a, num_r, s, (double)k1 * res, (double)k2 * res);
 }
 
 
@@ -260,6 +284,18 @@ int queue_blocks_per_cu(int num_r) {
 
 hipError_t launch_fit_f64(const FitArgs &a, hipStream_t st) { return launch<false>(a, st); }
 hipError_t launch_fit_mixed(const FitArgs &a, hipStream_t st) { return launch<true>(a, st); }
+
+hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, hipStream_t st) {
+  const dim3 grid((r.max_side * r.max_side + 255) / 256, a.n_src);
+  if (mixed) {
+    constexpr bool kMixed = true;
+    RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
+  } else {
+    constexpr bool kMixed = false;
+    RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_fit_queue(const FitArgs &a, const QueueArgs &q, int mixed, int blocks, hipStream_t st) {
   return mixed ? launch_q<true>(a, q, blocks, st) : launch_q<false>(a, q, blocks, st);

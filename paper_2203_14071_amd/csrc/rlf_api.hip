@@ -23,6 +23,7 @@ constexpr int kVersion = 100;                   // 0.1.0
 constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
 constexpr int kExtractChunk = 2048;             // sorted visibilities per extraction wave
 constexpr int kSortedPad = 64;                  // zero-weight tail of the sorted arrays
+constexpr int kMaxRefineLevel = 12;             // finest refinement step e_step / 4096
 
 }  // namespace
 
@@ -263,6 +264,8 @@ void free_facets(rlf_facets *f) {
   dfree(f->d_logw);
   dfree(f->d_lsurf);
   dfree(f->d_redo);
+  dfree(f->d_refine_win);
+  dfree(f->d_refine_l);
 }
 
 int check_device_error(rlf_ctx *c) {
@@ -754,6 +757,71 @@ int rlf_facets_free(rlf_facets *f) {
   }
   free_facets(f);
   delete f;
+  return RLF_OK;
+}
+
+int rlf_refine_sources(rlf_ctx *c, rlf_facets *f, int32_t np_max, double e_res, rlf_fit_out *out) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
+  if (!out || !out->flags) return fail(c, RLF_EINVAL, "out/out.flags is NULL");
+  if (np_max < 1 || !(e_res > 0) || !is_fin(e_res)) return fail(c, RLF_EINVAL, "np_max >= 1 and e_res > 0");
+  if (int e = set_device(c)) return e;
+  int last = 0;
+  while (last < kMaxRefineLevel && c->p.e_step / (double)(1 << last) > e_res) ++last;
+  if (last == 0) return RLF_OK;                          // the grid is already fine enough
+  if (c->p.e_step / (double)(1 << last) > e_res)
+    return fail(c, RLF_EINVAL, "e_res below e_step / 2^12");
+  constexpr int kSide = 64;
+  if (!f->d_refine_win) {
+    if (int e = dalloc(c, &f->d_refine_win, f->n_src * 5)) return e;
+    if (int e = dalloc(c, &f->d_refine_l, f->n_src * (int64_t)kSide * kSide)) return e;
+  }
+  RefineArgs r{};
+  r.n_src = (int32_t)f->n_src;
+  r.last_level = last;
+  r.np_max = np_max;
+  r.max_side = kSide;
+  r.unit = (int32_t)std::nearbyint(1.0 / c->p.e_step);
+  r.n_e = c->p.n_e;
+  r.n_valid = c->n_valid;
+  r.e_step = c->p.e_step;
+  r.log_frac = std::log(c->p.frac_thresh);
+  r.bad_sigma = c->p.bad_sigma;
+  r.bad_sqrtdet = c->p.bad_sqrtdet;
+  r.epts = c->d_epts;
+  r.lsurf = f->d_lsurf;
+  r.offsets = f->cells.offsets;
+  r.win = f->d_refine_win;
+  r.lloc = f->d_refine_l;
+  r.e1 = out->e1;
+  r.e2 = out->e2;
+  r.s1 = out->s1;
+  r.s2 = out->s2;
+  r.c12 = out->c12;
+  r.lmax = out->lmax;
+  r.n_above = out->n_above;
+  r.flags = out->flags;
+  FitArgs fa{};
+  fa.n_src = (int32_t)f->n_src;
+  fa.n_valid = c->n_valid;
+  fa.n_e = c->p.n_e;
+  fa.num_r = c->p.num_r;
+  fa.e_step = c->p.e_step;
+  fa.epts = c->d_epts;
+  fa.valid_index = c->d_vidx;
+  fa.sk = c->d_sk;
+  fa.logw = f->d_logw;
+  fa.offsets = f->cells.offsets;
+  fa.fit64 = f->cells.fit64;
+  fa.fit32 = f->cells.fit32;
+  fa.lsurf = f->d_lsurf;
+  HIPCHK(c, launch_refine_start(r, c->stream));
+  for (int level = 1; level <= last; ++level) {
+    r.level = level;
+    HIPCHK(c, launch_refine_eval(fa, r, f->mixed, c->stream));
+    HIPCHK(c, launch_refine_estimate(r, c->stream));
+  }
   return RLF_OK;
 }
 

@@ -149,6 +149,28 @@ struct FitArgs {
   double *lsurf;             // [n_src*n_valid] ln L(e) of the evaluated points
 };
 
+// Adaptive refinement: per source a window of integer lattice indices at
+// resolution e_step / 2^level; the estimate of each level decides the next.
+struct RefineArgs {
+  int32_t n_src;
+  int32_t level;             // current level (>= 1)
+  int32_t last_level;
+  int32_t np_max;            // stop when this many samples lie above the threshold
+  int32_t max_side;          // window points per axis, at most
+  int32_t unit;              // 1 / e_step (integer): |e| < 1 <=> k1^2 + k2^2 < (unit 2^level)^2
+  int32_t n_e, n_valid;
+  double e_step;
+  double log_frac, bad_sigma, bad_sqrtdet;
+  const int32_t *epts;       // coarse grid (level 0)
+  const double *lsurf;       // coarse ln L [n_src * n_valid]
+  const int64_t *offsets;    // facet cells (empty facets are left alone)
+  int32_t *win;              // [n_src * 5]: active, k1lo, k2lo, n1, n2
+  double *lloc;              // [n_src * max_side^2] ln L on the window
+  double *e1, *e2, *s1, *s2, *c12, *lmax;
+  int32_t *n_above;
+  uint32_t *flags;
+};
+
 // Work queue of the persistent likelihood kernel.
 struct QueueArgs {
   const int32_t *order;      // [n_rank] source of each rank (decreasing cell count)
@@ -220,6 +242,9 @@ hipError_t launch_fit_queue(const FitArgs &a, const QueueArgs &q, int mixed, int
 int fit_queue_blocks_per_cu(int mixed, int num_r);
 hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
+hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, hipStream_t st);
+hipError_t launch_refine_start(const RefineArgs &r, hipStream_t st);
+hipError_t launch_refine_estimate(const RefineArgs &r, hipStream_t st);
 hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t st);
 hipError_t launch_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t bits, uint32_t *dst,
                               hipStream_t st);

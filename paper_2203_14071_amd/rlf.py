@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librlf.so")
 
 RLF_OK, RLF_EINVAL, RLF_ENOMEM, RLF_EDEVICE, RLF_ERANGE, RLF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RLF_FP64, RLF_MIXED = 0, 1
-RLF_FLAG_BAD_VAR, RLF_FLAG_EMPTY, RLF_FLAG_EDGE, RLF_FLAG_FALLBACK, RLF_FLAG_REFIT = 1, 2, 4, 8, 16
+RLF_FLAG_BAD_VAR, RLF_FLAG_EMPTY, RLF_FLAG_EDGE, RLF_FLAG_FALLBACK, RLF_FLAG_REFIT, RLF_FLAG_REFINED = 1, 2, 4, 8, 16, 32
 RLF_MODEL_WRITE, RLF_MODEL_ACCUMULATE, RLF_MODEL_RESIDUAL = 0, 1, 2
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -80,6 +80,7 @@ _SIGNATURES = {
     "rlf_pass_create": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), _c_vp,
                          ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out), ctypes.c_char_p,
                          ctypes.POINTER(_c_vp)], ctypes.c_int),
+    "rlf_refine_sources": ([_c_vp, _c_vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(rlf_fit_out)], ctypes.c_int),
     "rlf_fit_sequential": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), ctypes.c_int64,
                             ctypes.c_int32, ctypes.POINTER(rlf_fit_out), _c_dp, _c_dp], ctypes.c_int),
     "rlf_pass_launch": ([_c_vp], ctypes.c_int),
@@ -240,6 +241,11 @@ class Context:
         flags (i32 viewed as u32), surface (f64) -- any may be absent except flags."""
         o, r = _fit_structs(out, mode, window, want_surface, fallback, check_stride)
         return self._check(lib().rlf_fit_sources(self.h, facets.h, ctypes.byref(o), ctypes.byref(r)))
+
+    def refine_sources(self, facets: "Facets", out: dict, np_max=30, e_res=0.003):
+        """Adaptive refinement of the last full-grid fit of `facets` (in place in `out`)."""
+        _, r = _fit_structs(out, 0, None, False, False)
+        return self._check(lib().rlf_refine_sources(self.h, facets.h, int(np_max), float(e_res), ctypes.byref(r)))
 
     def fit_sequential(self, obs: Obs, cat, chunk, out: dict, refit_bad=True, prior_mu=None):
         """Sequential sky-model refinement; `out` as for fit_sources (e1, e2,

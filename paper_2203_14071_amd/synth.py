@@ -73,6 +73,8 @@ class Config:
 # from tests/golden/make_noise_sigma.py (which evaluates the visibility model
 # with the oracle) and a test checks they still agree with that script.
 _SIGMA = {0: 0.00017231271326032695, 1: 0.006789083290568159, 3: 0.011537361476379389}
+# the facet-size experiment's noise on the config-1 coverage (same script)
+SIGMA_KSCAN = 0.0014667958180515958
 
 _CFG3_FREQS = tuple(962.5e6 + 25.0e6 * c for c in range(8))   # 8 x 25 MHz over 950-1150 MHz
 

@@ -216,3 +216,21 @@ def test_fused_residual_matches_explicit_residual(ctx):
         G.check_facet(a, s, ref, scale, cat.flux_jy[s] * 1.1)
         G.check_facet(b, s, ref, scale, cat.flux_jy[s] * 1.1)
     f1.free()
+
+
+@pytest.mark.parametrize("K", [20.0, 100.0])
+def test_facet_size_factor_matches_oracle(K):
+    """The facet-size factor K (Sec. 2.3) at the ends of the tuning scan."""
+    import dataclasses
+    cfg, o, cat, data = _field(0)
+    p = dataclasses.replace(oracle.Params(), K=K)
+    kctx = rlf.Context(0, None, rlf.params(K=K))
+    resid_g, fac_g, out_g, f = _run_all(o, cat, data, kctx)
+    resid_o, fac_o, fits_o = _oracle_all(o, cat, data, p)
+    scale = np.max(np.abs(resid_o))
+    for s in range(cat.n_src):
+        G.check_facet(fac_g, s, fac_o[s], scale, cat.flux_jy[s])
+        surf_o, est_o = fits_o[s]
+        G.check_fit(out_g, s, surf_o, G.oracle_estimate_variants(surf_o, p), out_g["surface"][s])
+    f.free()
+    kctx.close()

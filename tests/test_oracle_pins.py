@@ -480,6 +480,7 @@ def test_noise_sigma_constants_match_calibration_script():
     stored = json.load(open(os.path.join(GOLDEN, "noise_sigma.json")))
     for k in (0, 1, 3):
         assert synth.CONFIGS[k].noise_sigma_jy == stored[str(k)]
+    assert synth.SIGMA_KSCAN == stored["kscan"]
     assert mk.sigma_for(0) == pytest.approx(stored["0"], rel=1e-12)
 
 

@@ -2,7 +2,8 @@
 sources on the SKA-MID-like coverage for several facet-size factors K and
 measure the multiplicative and additive biases of the linear model
 e_measured - e_true = m e_true + c (per component), and the number of bad
-fits.
+fits.  Each fit is the full grid followed by the adaptive refinement around
+the maximum (the paper's sampler; rlf_refine_sources).
 
 Sources (stream +6 of the config-1 generator): the paper's population of
 faint star-forming galaxies, 10-200 uJy with pdf ~ S^-1.6, sizes from the
@@ -49,7 +50,8 @@ def bias_line(e_true, e_meas):
     return float(coef[0]), float(coef[1]), float(math.sqrt(cov[0, 0])), float(math.sqrt(cov[1, 1]))
 
 
-def run(Ks=(20, 30, 38, 50, 60, 70, 80, 100), n_src=1000, precision=rlf.RLF_FP64, device="cuda:0", log=None):
+def run(Ks=(20, 30, 38, 50, 60, 70, 80, 100), n_src=1000, precision=rlf.RLF_FP64, device="cuda:0", log=None,
+        refine=True):
     import torch
     cfg, cat = population(n_src)
     o = synth.observation(1)
@@ -67,7 +69,11 @@ def run(Ks=(20, 30, 38, 50, 60, 70, 80, 100), n_src=1000, precision=rlf.RLF_FP64
         ctx.extract_facets(obs, cat, obs.vis, f)           # true shapes: each facet is its own source + noise
         out = {k: torch.empty(n_src, dtype=torch.float64, device=device) for k in ("e1", "e2", "s1", "s2")}
         out["flags"] = torch.empty(n_src, dtype=torch.int32, device=device)
+        out["n_above"] = torch.empty(n_src, dtype=torch.int32, device=device)
         ctx.fit_sources(f, out)
+        grid_bad = int(((out["flags"] & rlf.RLF_FLAG_BAD_VAR) != 0).sum().item())
+        if refine:                                            # the paper's adaptive sampling around the maximum
+            ctx.refine_sources(f, out)
         ctx.sync()
         dt = time.perf_counter() - t0
         h = {k: v.cpu().numpy() for k, v in out.items()}
@@ -78,7 +84,8 @@ def run(Ks=(20, 30, 38, 50, 60, 70, 80, 100), n_src=1000, precision=rlf.RLF_FP64
         m1, c1, sm1, sc1 = bias_line(cat.e1[good], h["e1"][good])
         m2, c2, sm2, sc2 = bias_line(cat.e2[good], h["e2"][good])
         row = {"K": K, "m1": round(m1, 5), "m1_err": round(sm1, 5), "m2": round(m2, 5), "m2_err": round(sm2, 5),
-               "c1": round(c1, 5), "c2": round(c2, 5), "bad": int(np.sum(~good)),
+               "c1": round(c1, 5), "c2": round(c2, 5), "bad": int(np.sum(~good)), "bad_before_refinement": grid_bad,
+               "refined": int(np.sum((h["flags"] & rlf.RLF_FLAG_REFINED) > 0)),
                "mean_cells": round(float(cells.mean()), 1), "s": round(dt, 3)}
         rows.append(row)
         if log:

@@ -19,6 +19,13 @@ tool for accurate galaxy shape measurement with SKA" (arXiv 2203.14071):
   estimate.py    Sec. 2.4 and 4.1: mean and standard deviation of the
                  ellipticity samples above 5 % of the maximum likelihood,
                  the variance test for bad fits
+  position.py    Sec. 2.4: marginalisation over the source position with a
+                 uniform prior through the cross-correlation of the facet
+                 data with the model (reading in its docstring)
+  sequential.py  Sec. 2.1, 2.4, 3.1: chunked sequential sky-model refinement
+                 and the refit of bad fits
+  refine.py      Sec. 2.4: adaptive refinement of the sampled likelihood
+                 around its maximum (nested grids)
   mlp.py         the learned grid-narrowing network (not in the paper): an
                  FP64 forward/backward used to check the BF16 kernels
 
@@ -36,3 +43,4 @@ from .estimate import Estimate, estimate, FLAG_BAD_VAR, FLAG_EMPTY, FLAG_EDGE, F
 from .fit import Params, fit_source, fit_sources, narrowed_fit, window_rejected
 from .sequential import FLAG_REFIT, SkyCatalogue, fit_sequential
 from .refine import FLAG_REFINED, refine_source
+from .position import offset_grid, loglike_alpha_offsets, marginal_surface_pos, fit_source_pos

@@ -25,6 +25,7 @@ import numpy as np
 from .estimate import FLAG_BAD_VAR, FLAG_EMPTY
 from .fit import Params
 from .likelihood import alpha_knots, e_grid, log_alpha_weights, marginal_surface
+from .position import marginal_surface_pos, offset_grid
 
 FLAG_REFINED = 32
 MAX_SIDE = 64
@@ -59,9 +60,13 @@ def _scan(values, k1, k2, frac):
     return j, lmax, member
 
 
-def refine_source(facet, flux_jy, surface, est, p: Params = Params(), np_max=30, e_res=0.003, mu=None):
-    """surface, est: the full-grid fit of this facet (fit_source).  Returns
-    the refined estimate (or est itself when no refinement is needed)."""
+def refine_source(facet, flux_jy, surface, est, p: Params = Params(), np_max=30, e_res=0.003, mu=None,
+                  position=None):
+    """surface, est: the full-grid fit of this facet (fit_source, or
+    position.fit_source_pos with position = (n_side, step_arcsec), whose
+    position-marginalised likelihood the finer levels then use as well).
+    Returns the refined estimate (or est itself when no refinement is
+    needed)."""
     if est.flags & FLAG_EMPTY:
         return est
     i1, i2, _, _, valid = e_grid(p.n_e, p.e_step)
@@ -87,7 +92,11 @@ def refine_source(facet, flux_jy, surface, est, p: Params = Params(), np_max=30,
         e1, e2 = K1 * res, K2 * res
         vals = np.full(K1.shape, -np.inf)
         if np.any(ok):
-            vals[ok] = marginal_surface(facet, e1[ok], e2[ok], knots, logw)
+            if position is None:
+                vals[ok] = marginal_surface(facet, e1[ok], e2[ok], knots, logw)
+            else:
+                dl, dm = offset_grid(*position)
+                vals[ok] = marginal_surface_pos(facet, e1[ok], e2[ok], knots, logw, dl, dm)
         j, lmax, member = _scan(vals, K1, K2, p.frac)
         count = int(np.count_nonzero(member))
         wgt = np.exp(vals[member] - lmax)

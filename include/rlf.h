@@ -209,6 +209,25 @@ int rlf_facets_copy(rlf_ctx *ctx, const rlf_facets *facets, int64_t *offsets, in
 /* Free a facet object (NULL is a no-op).  Synchronises its context's stream. */
 int rlf_facets_free(rlf_facets *facets);
 
+/* Position marginalisation (Sec. 2.4: the likelihood is marginalised over
+ * the source position with a uniform prior, through the cross-correlation of
+ * the facet data with the model).  After this call, rlf_fit_sources (full
+ * grid) and rlf_refine_sources on `facets` use, for every e and knot,
+ *   D_p = sum_c W_c f_c Re(Vbar_c exp(-2 pi i (uc_c dl_p + vc_c dm_p))),
+ *   ln L(e) = ln sum_k w_{s,k} (1/n_side^2) sum_p exp(D_p^2 / (2 Mm) - ln(Mm)/2)
+ * over the offsets (dl_p, dm_p) = ((p1 - h) step, (p2 - h) step) of an
+ * n_side x n_side grid centred on the catalogue position, h = (n_side-1)/2,
+ * p = p1 * n_side + p2: a model displaced by x multiplies the facet model
+ * by exp(+2 pi i k.x) (the sign of Eq. 1), and the uniform prior over the
+ * square the grid spans is integrated as the mean over its points.
+ *   n_side        1 (position fixed, the default), 3, 5 or 7
+ *   step_arcsec   offset spacing in arcsec (> 0; ignored for n_side = 1)
+ * Allocates the cross-correlation rows (n_side^2 values per dense cell, FP64
+ * or FP32 with the facets' precision) on first use or growth; each fit
+ * recomputes them from the last extraction.  Windowed fits on such facets
+ * return RLF_EUNSUPPORTED.  RLF_EINVAL for another n_side or a step <= 0. */
+int rlf_facets_set_positions(rlf_ctx *ctx, rlf_facets *facets, int32_t n_side, double step_arcsec);
+
 /* Fit options. */
 typedef struct {
   int32_t mode;            /* 0 = full grid; 1 = windowed (window must be set)              */

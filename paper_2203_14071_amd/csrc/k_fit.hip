@@ -16,6 +16,15 @@
 //               each block of kBlock cells folded into FP64 totals, so the
 //               FP32 rounding error grows with kBlock, not with the cell count.
 // The epilogue (logs, exps, log-sum-exp over knots) is FP64 in both forms.
+//
+// Position marginalisation (Sec. 2.4; n_pos offsets x_p on a square grid,
+// uniform prior): D is formed per offset from the cross-correlation data
+// G[c, p] = W_c Re(Vbar_c exp(-2 pi i k_c.x_p)) and M is shared,
+//   ln L(e) = ln sum_k w_k (1/n_pos) sum_p exp(D_kp^2 / (2 M_k) - ln(M_k) / 2).
+// The knots run in blocks of KB with the KB * n_pos sums of a block in
+// registers; the n_pos values of a cell come in through scalar loads (one
+// row of G per cell), so a (cell, point, knot) costs the profile (6 ops), M
+// (2) and one FMA per offset, plus the quadratic form once per knot block.
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
 
@@ -114,20 +123,144 @@ __device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int
   return mx + log(acc);
 }
 
+// Knots per block of the position-marginalised sum: KB * NP partial sums
+// in registers (FP64, plus as many FP32 ones in the mixed form).
+constexpr int pos_knot_block(int np) { return np <= 9 ? 4 : (np <= 25 ? 2 : 1); }
+
+// Position-marginalised ln L(e) of source s at (e1, e2), |e| < 1; NaN for an
+// empty facet.
+template <int NP, bool kMixed>
+__device__ __forceinline__ double loglike_pos(const FitArgs &a, int num_r, int s, double e1, double e2) {
+  constexpr int KB = pos_knot_block(NP);
+  const double det = 1.0 - e1 * e1 - e2 * e2;
+  const double g = 1.0 / (det * det);
+  const int64_t c0 = a.offsets[s], c1 = a.offsets[s + 1];
+  if (c1 == c0) return NAN;
+  const double *lw = a.logw + (int64_t)s * a.num_r;
+  double mx = -INFINITY, acc = 0.0;
+  for (int k0 = 0; k0 < num_r; k0 += KB) {
+    double D[KB][NP], M[KB];
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      M[b] = 0.0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) D[b][p] = 0.0;
+    }
+    if (!kMixed) {
+      const double a11 = 1.0 + e1, a12 = e2, a22 = 1.0 - e1;
+      double sk[KB];
+#pragma unroll
+      for (int b = 0; b < KB; ++b) sk[b] = k0 + b < num_r ? a.sk[k0 + b] * g : 0.0;
+      const double4 *__restrict__ cells = a.fit64;
+      const double *__restrict__ G = a.pos_g64;
+      for (int64_t c = c0; c < c1; ++c) {
+        const double4 cl = cells[c];
+        const double ku = fma(a11, cl.x, a12 * cl.y);
+        const double kv = fma(a12, cl.x, a22 * cl.y);
+        const double q = fma(ku, ku, kv * kv);
+        const double *gc = G + c * NP;
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+          const double f = pow_m32_f64(fma(sk[b], q, 1.0));         // (2/3) f_c
+          M[b] = fma(cl.z * f, f, M[b]);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) D[b][p] = fma(f, gc[p], D[b][p]);
+        }
+      }
+    } else {
+      const float a11 = (float)(1.0 + e1), a12 = (float)e2, a22 = (float)(1.0 - e1);
+      float sk[KB];
+#pragma unroll
+      for (int b = 0; b < KB; ++b) sk[b] = k0 + b < num_r ? (float)(a.sk[k0 + b] * g) : 0.0f;
+      const float4 *__restrict__ cells = a.fit32;
+      const float *__restrict__ G = a.pos_g32;
+      auto block = [&](int64_t cb, int n) {
+        float d[KB][NP], m[KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+          m[b] = 0.0f;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) d[b][p] = 0.0f;
+        }
+        for (int t = 0; t < n; ++t) {
+          const float4 cl = cells[cb + t];
+          const float ku = fmaf(a11, cl.x, a12 * cl.y);
+          const float kv = fmaf(a12, cl.x, a22 * cl.y);
+          const float q = fmaf(ku, ku, kv * kv);
+          const float *gc = G + (cb + t) * NP;
+#pragma unroll
+          for (int b = 0; b < KB; ++b) {
+            const float r = __builtin_amdgcn_rsqf(fmaf(sk[b], q, 1.0f));
+            const float f = r * r * r;
+            m[b] = fmaf(cl.z * f, f, m[b]);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) d[b][p] = fmaf(f, gc[p], d[b][p]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+          M[b] += (double)m[b];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) D[b][p] += (double)d[b][p];
+        }
+      };
+      int64_t cb = c0;
+#pragma clang loop unroll(disable)
+      for (; cb + kBlock <= c1; cb += kBlock) block(cb, kBlock);
+      if (cb < c1) block(cb, (int)(c1 - cb));
+    }
+    // ln(w_k L(e, alpha_k, x_p)) in place of D, then one rescaling of the
+    // running sum per block
+    double bm = -INFINITY;
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      if (k0 + b < num_r) {
+        const double base = lw[k0 + b] - 0.5 * log(M[b]) - (kMixed ? 0.0 : kLnPowM32Scale);
+        const double h = 1.0 / (2.0 * M[b]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          D[b][p] = fma(D[b][p] * D[b][p], h, base);
+          bm = fmax(bm, D[b][p]);
+        }
+      }
+    }
+    const double nm = fmax(mx, bm);
+    double bs = 0.0;
+#pragma unroll
+    for (int b = 0; b < KB; ++b)
+      if (k0 + b < num_r) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bs += exp(D[b][p] - nm);
+      }
+    acc = (mx > -INFINITY ? acc * exp(mx - nm) : 0.0) + bs;
+    mx = nm;
+  }
+  return mx + log(acc / (double)NP);
+}
+
+// ln L(e): position fixed (NP = 0) or marginalised over NP offsets.
+template <int R, bool kExact, bool kMixed, int NP>
+__device__ __forceinline__ double loglike(const FitArgs &a, int num_r, int s, double e1, double e2) {
+  if constexpr (NP == 0)
+    return loglike_e<R, kExact, kMixed>(a, num_r, s, e1, e2);
+  else
+    return loglike_pos<NP, kMixed>(a, num_r, s, e1, e2);
+}
+
 // ln L(e) at valid grid point j (index into the valid-point list) of source s.
-template <int R, bool kExact, bool kMixed>
+template <int R, bool kExact, bool kMixed, int NP = 0>
 __device__ __forceinline__ void eval_point(const FitArgs &a, int num_r, int s, int j) {
   const int idx = a.epts[j];
   const int i1 = idx / a.n_e, i2 = idx - (idx / a.n_e) * a.n_e;
   const int ctr = (a.n_e - 1) / 2;
   a.lsurf[(int64_t)s * a.n_valid + j] =
-      loglike_e<R, kExact, kMixed>(a, num_r, s, (double)(i1 - ctr) * a.e_step, (double)(i2 - ctr) * a.e_step);
+      loglike<R, kExact, kMixed, NP>(a, num_r, s, (double)(i1 - ctr) * a.e_step, (double)(i2 - ctr) * a.e_step);
 }
 
 // Refinement level: one thread per point of the source's window at
 // resolution e_step / 2^level, e = k * that step, |e| < 1 tested on the
 // integers; -inf outside the domain.
-template <int R, bool kExact, bool kMixed>
+template <int R, bool kExact, bool kMixed, int NP = 0>
 __global__ __launch_bounds__(256) void k_refine_eval(FitArgs a, RefineArgs r, int num_r) {
   const int s = blockIdx.y;
   const int32_t *w = r.win + (int64_t)s * 5;
@@ -143,18 +276,18 @@ __global__ __launch_bounds__(256) void k_refine_eval(FitArgs a, RefineArgs r, in
     return;
   }
   const double res = a.e_step / (double)(1 << r.level);
-  *out = loglike_e<R, kExact, kMixed>(a, num_r, s, (double)k1 * res, (double)k2 * res);
+  *out = loglike<R, kExact, kMixed, NP>(a, num_r, s, (double)k1 * res, (double)k2 * res);
 }
 
 
 // Grid launch: blockIdx.y = source, one thread per valid grid point.
-template <int R, bool kExact, bool kMixed>
+template <int R, bool kExact, bool kMixed, int NP = 0>
 __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
   const int s = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_valid) return;
   if (a.redo && !a.redo[s]) return;
-  eval_point<R, kExact, kMixed>(a, num_r, s, j);
+  eval_point<R, kExact, kMixed, NP>(a, num_r, s, j);
 }
 
 // Windowed launch: blockIdx.y = source, one thread per position of the
@@ -250,9 +383,26 @@ __global__ void k_reset_counter(uint32_t *c) {
                          a.num_r);                                                                  \
   } while (0)
 
+// Position-marginalised launches: the offset count selects the kernel (the
+// knot count is a run-time bound there).
+#define RLF_POS_DISPATCH(KERNEL, GRID, ...)                                                             \
+  do {                                                                                                  \
+    if (a.n_pos == 9)                                                                                   \
+      hipLaunchKernelGGL((KERNEL<1, false, kMixed, 9>), GRID, dim3(256), 0, st, __VA_ARGS__, a.num_r);  \
+    else if (a.n_pos == 25)                                                                             \
+      hipLaunchKernelGGL((KERNEL<1, false, kMixed, 25>), GRID, dim3(256), 0, st, __VA_ARGS__, a.num_r); \
+    else if (a.n_pos == 49)                                                                             \
+      hipLaunchKernelGGL((KERNEL<1, false, kMixed, 49>), GRID, dim3(256), 0, st, __VA_ARGS__, a.num_r); \
+    else                                                                                                \
+      return hipErrorInvalidValue;                                                                      \
+  } while (0)
+
 template <bool kMixed>
 hipError_t launch(const FitArgs &a, hipStream_t st) {
-  if (a.window) {
+  if (a.n_pos) {
+    if (a.window) return hipErrorInvalidValue;          // full grid only
+    RLF_POS_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
+  } else if (a.window) {
     const int h = a.check_stride > 0 ? ((a.n_e - 1) / 2) / a.check_stride : 0;
     const int positions = a.n_e * a.n_e + (a.check_stride > 0 ? (2 * h + 1) * (2 * h + 1) : 0);
     RLF_FIT_DISPATCH(k_fit_window, dim3((positions + 255) / 256, a.n_src), a);
@@ -289,10 +439,16 @@ hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, 
   const dim3 grid((r.max_side * r.max_side + 255) / 256, a.n_src);
   if (mixed) {
     constexpr bool kMixed = true;
-    RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
+    if (a.n_pos)
+      RLF_POS_DISPATCH(k_refine_eval, grid, a, r);
+    else
+      RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
   } else {
     constexpr bool kMixed = false;
-    RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
+    if (a.n_pos)
+      RLF_POS_DISPATCH(k_refine_eval, grid, a, r);
+    else
+      RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
   }
   return hipGetLastError();
 }

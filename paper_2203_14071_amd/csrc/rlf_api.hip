@@ -266,6 +266,8 @@ void free_facets(rlf_facets *f) {
   dfree(f->d_redo);
   dfree(f->d_refine_win);
   dfree(f->d_refine_l);
+  if (f->d_pos_g) (void)hipFree(f->d_pos_g);
+  f->d_pos_g = nullptr;
 }
 
 int check_device_error(rlf_ctx *c) {
@@ -760,6 +762,36 @@ int rlf_facets_free(rlf_facets *f) {
   return RLF_OK;
 }
 
+int rlf_facets_set_positions(rlf_ctx *c, rlf_facets *f, int32_t n_side, double step_arcsec) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
+  if (n_side != 1 && n_side != 3 && n_side != 5 && n_side != 7) return fail(c, RLF_EINVAL, "n_side: 1, 3, 5 or 7");
+  if (n_side > 1 && !(step_arcsec > 0.0 && is_fin(step_arcsec)))
+    return fail(c, RLF_EINVAL, "step_arcsec must be positive and finite");
+  if (int e = set_device(c)) return e;
+  if (n_side > 1) {
+    const int64_t need = f->dense_total * (int64_t)n_side * n_side;
+    if (need > f->pos_cap) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));        // a queued fit may still read the old rows
+      if (f->d_pos_g) (void)hipFree(f->d_pos_g);
+      f->d_pos_g = nullptr;
+      f->pos_cap = 0;
+      hipError_t e = hipMalloc(&f->d_pos_g, (size_t)need * (f->mixed ? sizeof(float) : sizeof(double)));
+      if (e != hipSuccess) {
+        f->d_pos_g = nullptr;
+        (void)hipGetLastError();
+        f->pos_side = 1;
+        return fail(c, RLF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      }
+      f->pos_cap = need;
+    }
+  }
+  f->pos_side = n_side;
+  f->pos_step = n_side > 1 ? step_arcsec * kArcsec : 0.0;
+  return RLF_OK;
+}
+
 int rlf_refine_sources(rlf_ctx *c, rlf_facets *f, int32_t np_max, double e_res, rlf_fit_out *out) {
   if (!c) return RLF_EINVAL;
   c->err.clear();
@@ -803,19 +835,7 @@ int rlf_refine_sources(rlf_ctx *c, rlf_facets *f, int32_t np_max, double e_res, 
   r.n_above = out->n_above;
   r.flags = out->flags;
   FitArgs fa{};
-  fa.n_src = (int32_t)f->n_src;
-  fa.n_valid = c->n_valid;
-  fa.n_e = c->p.n_e;
-  fa.num_r = c->p.num_r;
-  fa.e_step = c->p.e_step;
-  fa.epts = c->d_epts;
-  fa.valid_index = c->d_vidx;
-  fa.sk = c->d_sk;
-  fa.logw = f->d_logw;
-  fa.offsets = f->cells.offsets;
-  fa.fit64 = f->cells.fit64;
-  fa.fit32 = f->cells.fit32;
-  fa.lsurf = f->d_lsurf;
+  if (int e = fit_args(c, f, fa)) return e;
   HIPCHK(c, launch_refine_start(r, c->stream));
   for (int level = 1; level <= last; ++level) {
     r.level = level;
@@ -837,6 +857,8 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   if (o.mode != 0 && o.mode != 1) return fail(c, RLF_EINVAL, "opts.mode");
   if (o.mode == 1 && !o.window) return fail(c, RLF_EINVAL, "windowed mode needs opts.window");
   if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
+  if (o.mode == 1 && f->pos_side > 1)
+    return fail(c, RLF_EUNSUPPORTED, "position marginalisation is implemented for the full grid only");
   if (int e = set_device(c)) return e;
   return enqueue_fit(c, f, o, *out, nullptr, 0);
 }
@@ -845,10 +867,8 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
 
 namespace rlf {
 
-int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
-                const QueueArgs *queue, int queue_blocks) {
-  const bool windowed = o.mode == 1;
-  FitArgs fa{};
+int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa) {
+  fa = FitArgs{};
   fa.n_src = (int32_t)f->n_src;
   fa.n_valid = c->n_valid;
   fa.n_e = c->p.n_e;
@@ -861,6 +881,35 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   fa.offsets = f->cells.offsets;
   fa.fit64 = f->cells.fit64;
   fa.fit32 = f->cells.fit32;
+  fa.lsurf = f->d_lsurf;
+  if (f->pos_side > 1) {
+    PosPrepArgs pa{};
+    pa.n_src = (int32_t)f->n_src;
+    pa.n_side = f->pos_side;
+    pa.n_pos = f->pos_side * f->pos_side;
+    pa.step = f->pos_step;
+    pa.src = f->d_src;
+    pa.offsets = f->cells.offsets;
+    pa.ix = f->cells.ix;
+    pa.iy = f->cells.iy;
+    pa.wsum = f->cells.wsum;
+    pa.vre = f->cells.vre;
+    pa.vim = f->cells.vim;
+    pa.g64 = f->mixed ? nullptr : (double *)f->d_pos_g;
+    pa.g32 = f->mixed ? (float *)f->d_pos_g : nullptr;
+    HIPCHK(c, launch_pos_prep(pa, f->mixed, c->stream));
+    fa.n_pos = pa.n_pos;
+    fa.pos_g64 = pa.g64;
+    fa.pos_g32 = pa.g32;
+  }
+  return RLF_OK;
+}
+
+int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
+                const QueueArgs *queue, int queue_blocks) {
+  const bool windowed = o.mode == 1;
+  FitArgs fa{};
+  if (int e = fit_args(c, f, fa)) return e;
   fa.window = windowed ? o.window : nullptr;
   fa.check_stride = (windowed && o.fallback) ? o.check_stride : 0;
   fa.redo = nullptr;

@@ -147,6 +147,26 @@ struct FitArgs {
   const int32_t *valid_index; // [n_e*n_e] flat grid index -> valid-point index, -1 if |e| >= 1
   const int32_t *redo;       // fallback pass: [n_src] nonzero = evaluate; null = all
   double *lsurf;             // [n_src*n_valid] ln L(e) of the evaluated points
+  // position marginalisation: n_pos offsets (0 = position fixed) and the
+  // cross-correlation data [cells * n_pos] of the form in use
+  int32_t n_pos;
+  const double *pos_g64;
+  const float *pos_g32;
+};
+
+// Cross-correlation data of the position marginalisation (one row of n_pos
+// values per compacted cell).
+struct PosPrepArgs {
+  int32_t n_src;
+  int32_t n_side;            // offsets per axis (odd)
+  int32_t n_pos;             // n_side^2
+  double step;               // offset spacing in radians
+  const SrcModel *src;       // theta per source
+  const int64_t *offsets;
+  const int32_t *ix, *iy;
+  const double *wsum, *vre, *vim;
+  double *g64;               // FP64 form
+  float *g32;                // mixed form
 };
 
 // Adaptive refinement: per source a window of integer lattice indices at
@@ -243,6 +263,7 @@ int fit_queue_blocks_per_cu(int mixed, int num_r);
 hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
 hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, hipStream_t st);
+hipError_t launch_pos_prep(const PosPrepArgs &a, int mixed, hipStream_t st);
 hipError_t launch_refine_start(const RefineArgs &r, hipStream_t st);
 hipError_t launch_refine_estimate(const RefineArgs &r, hipStream_t st);
 hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t st);

@@ -63,6 +63,13 @@ struct rlf_facets {
   int32_t *d_redo = nullptr;
   int32_t *d_refine_win = nullptr;           // refinement windows [n_src * 5] (made on first use)
   double *d_refine_l = nullptr;              // refinement window values [n_src * side^2]
+  // position marginalisation (rlf_facets_set_positions): offsets per axis
+  // (1 = position fixed), spacing in radians, cross-correlation data sized
+  // for every dense cell
+  int32_t pos_side = 1;
+  double pos_step = 0.0;
+  void *d_pos_g = nullptr;
+  int64_t pos_cap = 0;                       // rows x n_pos the buffer holds
 };
 
 
@@ -103,5 +110,9 @@ void dfree(T *&p) {
 // the persistent work-queue kernel instead of the grid launch.
 int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
                 const QueueArgs *queue, int queue_blocks);
+
+// Likelihood arguments of a facet object (position marginalisation
+// included); enqueues the cross-correlation data when offsets are set.
+int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa);
 
 }  // namespace rlf

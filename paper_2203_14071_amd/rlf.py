@@ -76,6 +76,7 @@ _SIGNATURES = {
     "rlf_facets_info": ([_c_vp, _c_vp, _c_lp, _c_lp, _c_lp], ctypes.c_int),
     "rlf_facets_copy": ([_c_vp, _c_vp, _c_lp, _c_ip, _c_ip, _c_ip, _c_dp, _c_dp, _c_dp], ctypes.c_int),
     "rlf_facets_free": ([_c_vp], ctypes.c_int),
+    "rlf_facets_set_positions": ([_c_vp, _c_vp, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     "rlf_fit_sources": ([_c_vp, _c_vp, ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out)], ctypes.c_int),
     "rlf_pass_create": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), _c_vp,
                          ctypes.POINTER(rlf_fit_opts), ctypes.POINTER(rlf_fit_out), ctypes.c_char_p,
@@ -241,6 +242,11 @@ class Context:
         flags (i32 viewed as u32), surface (f64) -- any may be absent except flags."""
         o, r = _fit_structs(out, mode, window, want_surface, fallback, check_stride)
         return self._check(lib().rlf_fit_sources(self.h, facets.h, ctypes.byref(o), ctypes.byref(r)))
+
+    def set_positions(self, facets: "Facets", n_side, step_arcsec=0.0):
+        """Marginalise later fits of `facets` over an n_side x n_side grid of
+        position offsets at spacing step_arcsec (n_side = 1: position fixed)."""
+        return self._check(lib().rlf_facets_set_positions(self.h, facets.h, int(n_side), float(step_arcsec)))
 
     def refine_sources(self, facets: "Facets", out: dict, np_max=30, e_res=0.003):
         """Adaptive refinement of the last full-grid fit of `facets` (in place in `out`)."""

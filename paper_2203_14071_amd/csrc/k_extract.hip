@@ -3,7 +3,9 @@
 // weighted result into the source's facet cell (rint(u theta), rint(v theta)).
 //
 // Work decomposition.  Lanes are sources: a wave holds 64 NS sources (NS per
-// lane, their constants in VGPRs) and walks a chunk of visibilities in the
+// lane, their constants in VGPRs; lane slots take the sources in order of
+// facet cell size, so the runs of a wave's lanes tend to end together and
+// the flushes diverge less) and walks a chunk of visibilities in the
 // facet object's uv-sorted order; each visibility's data is uniform across
 // the wave and arrives through scalar loads.  Along the sorted order every
 // source stays in one facet cell for long runs, so each lane accumulates
@@ -28,37 +30,44 @@ constexpr int kXcd = 8;
 constexpr int kWaves = 4;          // waves per block
 constexpr int kNsF64 = 2, kNsMixed = 2;        // sources per lane
 constexpr int kGroupF64 = 2, kGroupMixed = 4;  // visibilities whose scalar loads are issued together
-constexpr double kNoRun = -0.5;    // run key meaning "no run" (keys are integers)
+constexpr double kNoRun = 1099511627776.0;    // 2^40: "no open run" (run keys are below 2^31 in magnitude)
 
-// One source of a lane: facet geometry and the open run.
+// One source of a lane: facet geometry and the open run.  The run key is
+// iy * side + ix (an exact integer in FP64); base already holds the offset
+// half * (side + 1) of cell (0, 0) in the source's dense block.  The run's
+// visibility count is the lane-independent count of processed visibilities
+// now minus its value when the run started.
 struct LaneSrc {
   bool active;
   int64_t base;
-  double half, side, koff;         // key = iy side + ix + koff
-  double key, rw, rzr, rzi, rn;
+  double half, side;
+  double key, rw, rzr, rzi;
+  int32_t start;
 };
 
 // Add the open run to its dense cell: four FP64 atomics at one address (the
 // count is an exact integer in FP64).
-__device__ __forceinline__ void flush(double4 *__restrict__ acc, const LaneSrc &L) {
+__device__ __forceinline__ void flush(double4 *__restrict__ acc, const LaneSrc &L, int32_t nproc) {
   double *c = &acc[L.base + (int32_t)L.key].x;
   unsafeAtomicAdd(c, L.rw);
   unsafeAtomicAdd(c + 1, L.rzr);
   unsafeAtomicAdd(c + 2, L.rzi);
-  unsafeAtomicAdd(c + 3, L.rn);
+  unsafeAtomicAdd(c + 3, (double)(nproc - L.start));
 }
 
-__device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, double ww, double xf,
-                                     double yf, double zr, double zi) {
-  const double k = fma(yf, L.side, xf + L.koff);
+// One visibility of one lane source; nproc = visibilities of the chunk with
+// weight > 0 processed before this one (uniform).
+__device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, int32_t nproc,
+                                     double ww, double xf, double yf, double zr, double zi) {
+  const double k = fma(yf, L.side, xf);
   if (k != L.key) {
-    if (L.key >= 0.0 && L.active) flush(acc, L);
+    if (L.key != kNoRun && L.active) flush(acc, L, nproc);
     const bool inb = fabs(xf) <= L.half && fabs(yf) <= L.half;
     if (!inb && L.active) atomicOr(err, 1u);
     L.key = inb ? k : kNoRun;
-    L.rn = L.rw = L.rzr = L.rzi = 0.0;
+    L.start = nproc;
+    L.rw = L.rzr = L.rzi = 0.0;
   }
-  L.rn += 1.0;
   L.rw += ww;
   L.rzr = fma(ww, zr, L.rzr);
   L.rzi = fma(ww, zi, L.rzi);
@@ -73,17 +82,17 @@ __device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint
 // A lane may hold NS sources (NS * 64 per wave) to share each load.
 //
 // Cell index: ix = rint(fl(u theta)) and iy likewise, in FP64 (exact
-// integers); the run key (iy + half) side + (ix + half) is formed in FP64 too
-// (exact: |key| < 2^31) and compared as a double, so the common path has no
+// integers); the run key iy side + ix is formed in FP64 too (one FMA, exact:
+// |key| < 2^31) and compared as a double, so the common path has no
 // conversions.  The facet half-size was sized on the host from the largest
 // |u|, |v| with the same rounding chain, so every index is inside its facet;
 // the bound is still checked whenever a run starts (err bit 0).
 template <bool kMixed, int NS, int G>
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 : 5, 16))) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
                                                  const void *__restrict__ squad, const void *__restrict__ sres,
                                                  const uint64_t *__restrict__ swt,
                                                  double4 *__restrict__ acc) {
-  __shared__ double2 tab[kMixed ? 1 : kCisTable + 1];
+  __shared__ double2 tab[kMixed ? 1 : kCisTable];
   if (!kMixed) {
     cis_table_init(tab);
     __syncthreads();
@@ -102,15 +111,16 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double4 *_
   for (int i = 0; i < NS; ++i) {
     const int s_raw = (tile * NS + i) * 64 + lane;
     L[i].active = s_raw < a.n_src;
-    src[i] = L[i].active ? s_raw : a.n_src - 1;
+    src[i] = a.order[L[i].active ? s_raw : a.n_src - 1];
     const SrcGeom g = a.geom[src[i]];
-    L[i].base = g.base;
+    L[i].base = g.base + (int64_t)g.half * (g.side + 1);
     L[i].half = (double)g.half;
     L[i].side = (double)g.side;
-    L[i].koff = L[i].half * (L[i].side + 1.0);
     L[i].key = kNoRun;
-    L[i].rn = L[i].rw = L[i].rzr = L[i].rzi = 0.0;
+    L[i].start = 0;
+    L[i].rw = L[i].rzr = L[i].rzi = 0.0;
   }
+  int32_t nproc = 0;
   const int64_t j0 = chunk * (int64_t)a.chunk;
   const int len = (int)(min(a.sv.n_vis, j0 + (int64_t)a.chunk) - j0);
   const double4 *__restrict__ geo = sgeo + j0;
@@ -150,9 +160,10 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double4 *_
           const double zi = fma(rg[t].y, cs.x, -(rg[t].x * cs.y));
           const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, 1.0)));
           zr = fma(gg[t].w * sflux[i], pow_m32_f64(x), zr);         // own model, real after the shift
-          step(L[i], acc, a.err, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
+          step(L[i], acc, a.err, nproc, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
                zr, zi);
         }
+        ++nproc;
       }
     }
   } else {
@@ -188,15 +199,16 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a, const double4 *_
           const float x = fmaf(p[i].q11, qg[t].x, fmaf(p[i].q12x2, qg[t].y, fmaf(p[i].q22, qg[t].z, 1.0f)));
           const float q = __builtin_amdgcn_rsqf(x);
           zr = fmaf(qg[t].w * p[i].flux, q * q * q, zr);
-          step(L[i], acc, a.err, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
+          step(L[i], acc, a.err, nproc, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
                (double)zr, (double)zi);
         }
+        ++nproc;
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < NS; ++i)
-    if (L[i].key >= 0.0 && L[i].active) flush(acc, L[i]);
+    if (L[i].key != kNoRun && L[i].active) flush(acc, L[i], nproc);
 }
 
 }  // namespace

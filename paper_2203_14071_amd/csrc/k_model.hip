@@ -2,11 +2,12 @@
 // every catalogue source.
 //
 // One thread per visibility and a uniform loop over sources: the source
-// record comes in through scalar loads shared by the wave.  Work per
+// records come in two at a time through scalar loads shared by the wave.  Work per
 // (visibility, source) pair:
 //   FP64 form:  phase (3 FMA), exp(2 pi i phase) by exact reduction + LDS
-//               table + short polynomials (~16 ops), profile
-//               (3 FMA + corrected rsqrt cube, 5 ops, + 2 MUL), 2 FMA into the sum;
+//               table + short polynomials (~15 ops), profile
+//               (3 FMA + corrected rsqrt cube, 5 ops, + 1 MUL), 2 FMA into the
+//               sum (the profile's constant 3/2 is applied once at the end);
 //   mixed form: phase and its reduction to [-1/2, 1/2] turns in FP64, then
 //               v_sin/v_cos (argument in turns), profile and sum in FP32.
 // Two entry kernels: visibilities in caller order (rlf_model_vis), and the
@@ -22,16 +23,26 @@ __device__ __forceinline__ double2 sum_f64(double u, double v, double w, const S
                                            int e, const double2 *tab) {
   const double uu = u * u, uv = u * v, vv = v * v;
   double ar = 0.0, ai = 0.0;
-  for (int s = b; s < e; ++s) {
-    const SrcModel p = src[s];
+  auto term = [&](const SrcModel &p) {
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
     const double2 cs = cis2pi_f64(ph, tab);
     const double x = fma(p.q11, uu, fma(p.q12x2, uv, fma(p.q22, vv, 1.0)));
-    const double amp = (kPowM32Scale * p.flux) * pow_m32_f64(x);
+    const double amp = p.flux * pow_m32_f64(x);             // (2/3) of the term's amplitude
     ar = fma(amp, cs.x, ar);
     ai = fma(amp, cs.y, ai);
+  };
+  // two source records per step: both scalar loads are in flight together
+  struct Two {
+    SrcModel p0, p1;
+  };
+  int s = b;
+  for (; s + 1 < e; s += 2) {
+    const Two t = *reinterpret_cast<const Two *>(src + s);
+    term(t.p0);
+    term(t.p1);
   }
-  return make_double2(ar, ai);
+  if (s < e) term(src[s]);
+  return make_double2(kPowM32Scale * ar, kPowM32Scale * ai);
 }
 
 __device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const SrcMixed *__restrict__ src, int b,
@@ -39,8 +50,7 @@ __device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const 
   const float uf = (float)u, vf = (float)v;
   const float uu = uf * uf, uv = uf * vf, vv = vf * vf;
   float ar = 0.0f, ai = 0.0f;
-  for (int s = b; s < e; ++s) {
-    const SrcMixed p = src[s];
+  auto term = [&](const SrcMixed &p) {
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
     const float t = (float)(ph - rint(ph));                 // turns, |t| <= 1/2
     const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
@@ -49,13 +59,23 @@ __device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const 
     const float amp = p.flux * (r * r * r);
     ar = fmaf(amp, cs, ar);
     ai = fmaf(amp, sn, ai);
+  };
+  struct Two {
+    SrcMixed p0, p1;
+  };
+  int s = b;
+  for (; s + 1 < e; s += 2) {
+    const Two t = *reinterpret_cast<const Two *>(src + s);
+    term(t.p0);
+    term(t.p1);
   }
+  if (s < e) term(src[s]);
   return make_float2(ar, ai);
 }
 
 template <bool kMixed>
 __global__ __launch_bounds__(256) void k_model(ModelArgs a) {
-  __shared__ double2 tab[kCisTable + 1];
+  __shared__ double2 tab[kCisTable];
   if (!kMixed) {
     cis_table_init(tab);
     __syncthreads();
@@ -109,7 +129,7 @@ __global__ __launch_bounds__(256) void k_model(ModelArgs a) {
 // Residual (or a plain gather) into the uv-sorted order, plus the weights.
 template <bool kMixed>
 __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
-  __shared__ double2 tab[kCisTable + 1];
+  __shared__ double2 tab[kCisTable];
   if (!kMixed && a.subtract) {
     cis_table_init(tab);
     __syncthreads();

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -250,6 +251,7 @@ void free_facets(rlf_facets *f) {
   }
   f->sv = Sorted{};
   dfree(f->d_geom);
+  dfree(f->d_order);
   dfree(f->acc.cell);
   dfree(f->cells.offsets);
   dfree(f->cells.n_nonempty);
@@ -585,6 +587,7 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     if ((rc = dalloc(c, &f->d_src, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_src32, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_geom, f->n_src))) break;
+    if ((rc = dalloc(c, &f->d_order, f->n_src))) break;
     if ((rc = dalloc(c, &f->acc.cell, total))) break;
     if ((rc = dalloc(c, &f->cells.offsets, f->n_src + 1))) break;
     if ((rc = dalloc(c, &f->cells.n_nonempty, f->n_src))) break;
@@ -610,6 +613,14 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
   }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpy(f->d_geom, f->geom.data(), sizeof(SrcGeom) * f->geom.size(), hipMemcpyHostToDevice);
+  // extraction lanes take the sources in order of cell size: cell boundaries
+  // (rint(u theta)) of neighbouring lanes then nearly coincide, so their runs
+  // end at nearly the same visibilities and the flushes of a wave cluster
+  std::vector<int32_t> order((size_t)f->n_src);
+  for (int64_t s = 0; s < f->n_src; ++s) order[(size_t)s] = (int32_t)s;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return f->theta[(size_t)x] < f->theta[(size_t)y]; });
+  if (e == hipSuccess) e = hipMemcpy(f->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(f->acc.cell, 0, sizeof(double4) * (size_t)total);
   if (e == hipSuccess) e = hipMemset(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1));
@@ -694,6 +705,7 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
   a.src = f->d_src;
   a.src32 = f->d_src32;
   a.geom = f->d_geom;
+  a.order = f->d_order;
   a.acc = f->acc;
   a.err = c->d_err;
   e = launch_extract(a, f->mixed, c->stream);

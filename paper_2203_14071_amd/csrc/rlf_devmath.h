@@ -1,14 +1,16 @@
 // Device math used by the kernels.
 //
 // cis2pi_f64: exp(2 pi i phi) in FP64 for phase arguments of thousands of
-// turns.  Reduction is exact: r = phi - rint(phi) in [-1/2, 1/2] (the
-// difference is a multiple of ulp(phi) no larger than 1/2, so it is
-// representable), k = rint(1024 r), d = r - k/1024 in [-1/2048, 1/2048]
-// (again exact).  exp(2 pi i r) = T[k] * exp(2 pi i d) with
-// T[k] = exp(2 pi i k/1024) from a 1025-entry table in LDS (16.4 KB), and
-// exp(i x), |x| <= pi/1024 < 3.1e-3, from its Taylor series: cos to x^4
+// turns.  Reduction is exact: m = phi + 1.5 * 2^42 rounds phi to the
+// nearest multiple k / 1024 of 1/1024 turn (ties to even) for
+// |phi| < 2^41, k / 1024 = m - 1.5 * 2^42 and d = phi - k / 1024 in
+// [-1/2048, 1/2048] are exact, and k mod 1024 is the low ten bits of m's
+// mantissa.  Then exp(2 pi i phi) = T[k mod 1024] * exp(i x), x = 2 pi d,
+// with T[j] = exp(2 pi i j / 1024) from a 1024-entry table in LDS (16 KB),
+// and exp(i x), |x| <= pi/1024 < 3.1e-3, from its Taylor series: cos to x^4
 // (truncation < x^6/6! < 1.2e-18) and sin to x^5 (truncation
-// < x^7/7! < 4.3e-22).  About 16 VALU operations.
+// < x^7/7! < 4.3e-22).  About 15 VALU operations; the table index is in
+// range whatever phi is.
 //
 // pow_m32_f64: (2/3) x^(-3/2) for x >= 1 from v_rsq_f64 (relative error
 // ~2^-24) with one correction: with y = rsq(x), x^(-3/2) = y^3 (1 + 3e/2 +
@@ -25,28 +27,29 @@ namespace rlf {
 
 constexpr int kCisTable = 1024;                 // table steps per turn
 
-// Fill the block's LDS table (257 entries, k = -128..128).  Call from every
-// thread of the block, followed by __syncthreads().
+// Fill the block's LDS table (kCisTable entries).  Call from every thread of
+// the block, followed by __syncthreads().
 __device__ __forceinline__ void cis_table_init(double2 *tab) {
-  for (int k = threadIdx.x; k <= kCisTable; k += blockDim.x) {
+  for (int k = threadIdx.x; k < kCisTable; k += blockDim.x) {
     double s, c;
-    sincospi((double)(k - kCisTable / 2) * (2.0 / kCisTable), &s, &c);
+    sincospi((double)k * (2.0 / kCisTable), &s, &c);
     tab[k] = make_double2(c, s);
   }
 }
 
+constexpr double kTurnMagic = 6597069766656.0;   // 1.5 * 2^42: adding it rounds to 1/1024 turn
+
 // (cos 2 pi phi, sin 2 pi phi) with the table above.
 __device__ __forceinline__ double2 cis2pi_f64(double phi, const double2 *tab) {
-  const double r = phi - rint(phi);
-  const double kf = rint(r * (double)kCisTable);
-  const double d = fma(kf, -1.0 / kCisTable, r);
-  const double x = d * 6.283185307179586476925286766559;   // 2 pi
+  const double m = phi + kTurnMagic;
+  const double d = phi - (m - kTurnMagic);
+  const double x = d * 6.283185307179586476925286766559;
   const double x2 = x * x;
   // cos x = 1 - x^2/2 + x^4/24;  sin x = x (1 - x^2/6 + x^4/120)
   const double cx = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0);
   const double sx = x * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
-  const double2 t = tab[(int)kf + kCisTable / 2];
-  return make_double2(fma(t.x, cx, -(t.y * sx)), fma(t.x, sx, t.y * cx));
+  const double2 tv = tab[(uint32_t)__double2loint(m) & (uint32_t)(kCisTable - 1)];
+  return make_double2(fma(tv.x, cx, -(tv.y * sx)), fma(tv.x, sx, tv.y * cx));
 }
 
 // (2/3) x^(-3/2), x >= 1 and finite.

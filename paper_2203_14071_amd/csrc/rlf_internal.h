@@ -104,6 +104,7 @@ struct ExtractArgs {
   const SrcModel *src;
   const SrcMixed *src32;
   const SrcGeom *geom;
+  const int32_t *order;      // [n_src] source of each lane slot: sources by increasing theta
   DenseAcc acc;
   uint32_t *err;             // bit 0: a cell index fell outside its facet (visibility skipped)
 };

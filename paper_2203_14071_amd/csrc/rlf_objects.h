@@ -55,6 +55,7 @@ struct rlf_facets {
   SrcModel *d_src = nullptr;
   SrcMixed *d_src32 = nullptr;
   SrcGeom *d_geom = nullptr;
+  int32_t *d_order = nullptr;                // sources by increasing theta (extraction lanes)
   Sorted sv{};                               // uv-sorted visibility layout
   DenseAcc acc{};
   Cells cells{};

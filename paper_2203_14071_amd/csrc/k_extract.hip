@@ -55,10 +55,12 @@ __device__ __forceinline__ void flush(double4 *__restrict__ acc, const LaneSrc &
   unsafeAtomicAdd(c + 3, (double)(nproc - L.start));
 }
 
-// One visibility of one lane source; nproc = visibilities of the chunk with
-// weight > 0 processed before this one (uniform).
-__device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, int32_t nproc,
-                                     double ww, double xf, double yf, double zr, double zi) {
+// Run bookkeeping of one lane source at one visibility (nproc = visibilities
+// of the chunk with weight > 0 processed before this one, uniform): when the
+// cell changes, flush the open run and start a new one.  The caller then adds
+// the visibility's terms to the run sums.
+__device__ __forceinline__ void enter_cell(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, int32_t nproc,
+                                           double xf, double yf) {
   const double k = fma(yf, L.side, xf);
   if (k != L.key) {
     if (L.key != kNoRun && L.active) flush(acc, L, nproc);
@@ -68,17 +70,16 @@ __device__ __forceinline__ void step(LaneSrc &L, double4 *__restrict__ acc, uint
     L.start = nproc;
     L.rw = L.rzr = L.rzi = 0.0;
   }
-  L.rw += ww;
-  L.rzr = fma(ww, zr, L.rzr);
-  L.rzi = fma(ww, zi, L.rzi);
 }
 
 // The read-only visibility data and the atomic targets are separate
 // restrict-qualified kernel parameters: with no possible aliasing the
 // compiler keeps the per-visibility loads scalar (s_load) although the loop
 // issues atomics.  Per visibility the wave loads (u, v, w, spec), the
-// profile's quadratic terms, the residual and the weight; flagged
-// visibilities carry weight +0 and are skipped on a scalar test of the bits.
+// profile's quadratic terms, the residual and the weight (FP64 form: the
+// weighted residual w R and w spec, so that the run sums take the shifted
+// residual and the own model in three FMAs and two); flagged visibilities
+// carry weight +0 and are skipped on a scalar test of the bits.
 // A lane may hold NS sources (NS * 64 per wave) to share each load.
 //
 // Cell index: ix = rint(fl(u theta)) and iy likewise, in FP64 (exact
@@ -156,12 +157,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
         for (int i = 0; i < NS; ++i) {
           const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
           const double2 cs = cis2pi_f64(ph, tab);
-          double zr = fma(rg[t].x, cs.x, rg[t].y * cs.y);           // residual * exp(-2 pi i ph)
-          const double zi = fma(rg[t].y, cs.x, -(rg[t].x * cs.y));
           const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, 1.0)));
-          zr = fma(gg[t].w * sflux[i], pow_m32_f64(x), zr);         // own model, real after the shift
-          step(L[i], acc, a.err, nproc, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
-               zr, zi);
+          const double own = sflux[i] * pow_m32_f64(x);             // own model / spec, real after the shift
+          enter_cell(L[i], acc, a.err, nproc, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)));
+          // w z = (w R) exp(-2 pi i ph) + (w spec) own
+          L[i].rw += ww;
+          L[i].rzr = fma(rg[t].x, cs.x, fma(rg[t].y, cs.y, fma(qg[t].w, own, L[i].rzr)));
+          L[i].rzi = fma(rg[t].y, cs.x, fma(-rg[t].x, cs.y, L[i].rzi));
         }
         ++nproc;
       }
@@ -199,8 +201,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
           const float x = fmaf(p[i].q11, qg[t].x, fmaf(p[i].q12x2, qg[t].y, fmaf(p[i].q22, qg[t].z, 1.0f)));
           const float q = __builtin_amdgcn_rsqf(x);
           zr = fmaf(qg[t].w * p[i].flux, q * q * q, zr);
-          step(L[i], acc, a.err, nproc, ww, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)),
-               (double)zr, (double)zi);
+          enter_cell(L[i], acc, a.err, nproc, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)));
+          L[i].rw += ww;
+          L[i].rzr = fma(ww, (double)zr, L[i].rzr);
+          L[i].rzi = fma(ww, (double)zi, L[i].rzi);
         }
         ++nproc;
       }

@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void k_model(ModelArgs a) {
   }
 }
 
-// Residual (or a plain gather) into the uv-sorted order, plus the weights.
+// Residual (or a plain gather) into the uv-sorted order, plus the weights;
+// the FP64 form stores w R and w spec, the products its extraction uses.
 template <bool kMixed>
 __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
   __shared__ double2 tab[kCisTable];
@@ -142,13 +143,17 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
   // kernel can have clobbered stay scalar (one s_load per source per wave).
   const double w = kMixed ? (double)reinterpret_cast<const float *>(a.weight)[i]
                           : reinterpret_cast<const double *>(a.weight)[i];
+  const double wpos = w > 0.0 ? w : 0.0;
   if (!kMixed) {
     double2 r = reinterpret_cast<const double2 *>(a.vis)[i];
     if (a.subtract) {
       const double2 acc = sum_f64(g.x, g.y, g.z, a.src, 0, a.n_src, tab);
       r = make_double2(fma(-g.w, acc.x, r.x), fma(-g.w, acc.y, r.y));
     }
-    reinterpret_cast<double2 *>(a.sv.res)[j] = r;
+    // FP64 form: the weighted residual, and the weight times the spectral
+    // factor in the fourth slot of the quadratic terms
+    reinterpret_cast<double2 *>(a.sv.res)[j] = make_double2(wpos * r.x, wpos * r.y);
+    reinterpret_cast<double4 *>(a.sv.quad)[j].w = wpos * g.w;
   } else {
     float2 r = reinterpret_cast<const float2 *>(a.vis)[i];
     if (a.subtract) {
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
     reinterpret_cast<float2 *>(a.sv.res)[j] = r;
   }
   // flagged weights (<= 0 or NaN) are stored as +0: the extraction tests bits
-  a.sv.wt[j] = w > 0.0 ? w : 0.0;
+  a.sv.wt[j] = wpos;
 }
 
 }  // namespace

@@ -79,8 +79,9 @@ struct Sorted {
   int64_t n_vis;
   uint32_t *order;           // sorted position -> visibility index row*n_chan + chan
   double4 *geo;              // (u, v, w) in wavelengths, spectral factor (nu_c/nu_ref)^beta
-  void *quad;                // (u^2, u v, v^2, _) double4 | (same in FP32 from (float)u, (float)v, spec) float4
-  void *res;                 // residual, complex128 | complex64
+  void *quad;                // (u^2, u v, v^2, w spec) double4, w spec of the last residual gather |
+                             // (u^2, u v, v^2 in FP32 from (float)u, (float)v; spec) float4
+  void *res;                 // weighted residual w R, complex128 | residual R, complex64
   double *wt;                // weight, 0 where w <= 0 or NaN (flagged)
 };
 

@@ -50,7 +50,7 @@ MODEL_FLOP_PAIR = 19
 # reading), for the kernel as it is now; None where not measured.
 # (profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md: fetch 1633.6 / 1219.1 MB,
 # write 6046.6 MB, nearly all of it the memory-side run-flush atomics)
-EXTRACT_TRAFFIC_BYTES = {"fp64": 7680.2e6, "mixed": 7265.7e6}
+EXTRACT_TRAFFIC_BYTES = {"fp64": 8037.9e6, "mixed": 8469.4e6}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Slots per unit of work count the method's necessary operations at their
 # measured gfx950 cost (FP64 and FP32 add/mul/FMA/round 1, v_sin/v_cos/v_rsq
@@ -66,8 +66,8 @@ EXTRACT_TRAFFIC_BYTES = {"fp64": 7680.2e6, "mixed": 7265.7e6}
 #     amplitude 1, accumulate 2;  mixed 20 = phase 3, reduction 3, sin + cos 4,
 #     profile 3 + rsq 2 + cube 2, amplitude 1, accumulate 2
 SLOT_PEAK = 256 * 64 * 2.4e9
-SLOTS = {"fp64": {"extract": 46, "fit_knot": 12, "fit_point": 5, "model": 32},
-         "mixed": {"extract": 36, "fit_knot": 8, "fit_point": 5, "model": 20}}
+SLOTS = {"fp64": {"extract": 44, "fit_knot": 12, "fit_point": 5, "model": 33},
+         "mixed": {"extract": 31, "fit_knot": 7, "fit_point": 10, "model": 17}}
 
 
 def log(*a):
@@ -98,6 +98,11 @@ def cpu_baseline(o, vis_true_fn, cat, n_sample, p):
                 host_cores_available=len(os.sched_getaffinity(0)))
 
 
+def _values(text, typ):
+    """Comma-separated list of values; '' or 'none' is the empty list."""
+    return [] if text in ("", "none") else [typ(v) for v in text.split(",")]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,12 +121,12 @@ def main():
                     help="training source populations to compare (config-1 generator either way)")
     ap.add_argument("--check-stride", type=int, default=4)
     ap.add_argument("--kscan", default="20,30,38,50,60,70,80,100",
-                    help="facet-size factors K of the tuning experiment ('' = skip)")
+                    help="facet-size factors K of the tuning experiment ('' or none = skip)")
     ap.add_argument("--seq-chunks", default="1000,100,10",
-                    help="chunk sizes of the sequential sky-model refinement to time ('' = skip)")
+                    help="chunk sizes of the sequential sky-model refinement to time ('' or none = skip)")
     ap.add_argument("--pos-sigma", default="0.1,0.3",
                     help="catalogue position errors (arcsec, per axis) of the position-marginalisation "
-                         "experiment ('' = skip)")
+                         "experiment ('' or none = skip)")
     ap.add_argument("--pos-sides", default="3,5,7", help="offset grids (per axis) to compare with the fixed position")
     ap.add_argument("--full-frac", type=float, default=0.25,
                     help="windows above this fraction of the grid are fitted on the whole grid")
@@ -152,10 +157,8 @@ def main():
                                        [float(v) for v in args.nsigma.split(",")], pops, args.check_stride,
                                        args.full_frac)), flush=True)
         return
-    main_form = run_form(args.precision, args.steps, args.warmup,
-                         [int(v) for v in args.seq_chunks.split(",")] if args.seq_chunks else [],
-                         [float(v) for v in args.pos_sigma.split(",")] if args.pos_sigma and not args.only else [],
-                         [int(v) for v in args.pos_sides.split(",")])
+    main_form = run_form(args.precision, args.steps, args.warmup, _values(args.seq_chunks, int),
+                         [] if args.only else _values(args.pos_sigma, float), _values(args.pos_sides, int))
     res = main_form["json"]
     if args.only:
         print(json.dumps(res), flush=True)
@@ -178,10 +181,10 @@ def main():
                                                      [float(v) for v in args.nsigma.split(",")],
                                                      pops, args.check_stride,
                                                      args.full_frac)
-    if args.kscan:
+    if _values(args.kscan, int):
         from paper_2203_14071_amd import kscan
         t0 = time.perf_counter()
-        rows = kscan.run([int(v) for v in args.kscan.split(",")], log=log)
+        rows = kscan.run(_values(args.kscan, int), log=log)
         res["facet_size_scan"] = {
             "what": "1000 single sources, 10-200 uJy, noise for SNR 19 at 10 uJy, config-1 coverage; "
                     "e_measured - e_true = m e_true + c over good fits (Sec. 4.2)",

@@ -19,6 +19,8 @@
 // Integer results are exact (cell index in FP64 exactly as rint(fl(u theta)));
 // FP sums are atomic and order-dependent in their last bits.  Runs are summed
 // in FP64 in both forms (the mixed form's FP32 terms are widened per term).
+#include <algorithm>
+
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
 
@@ -215,6 +217,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
     if (L[i].key != kNoRun && L[i].active) flush(acc, L[i], nproc);
 }
 
+// Resident blocks of an extraction kernel on the current device (cached).
+template <class K>
+int64_t resident_blocks(K kernel, int slot) {
+  static int64_t cache[2][16] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+  if (!cache[slot][dev]) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    cache[slot][dev] = (int64_t)per_cu * cus;
+  }
+  return cache[slot][dev];
+}
+
+// Visibilities per wave: near a nominal 2048, sized so the grid is a whole
+// number of rounds of resident blocks (a last round nearly empty would leave
+// the chip idle for a whole block's duration).
+int64_t chunk_size(int64_t n_vis, int64_t bpc, int64_t capacity) {
+  constexpr int64_t kNominal = 2048, kMin = 256;
+  auto blocks = [&](int64_t chunk) { return ((n_vis + chunk - 1) / chunk + kXcd - 1) / kXcd * kXcd * bpc; };
+  if (capacity <= 0 || n_vis <= 0) return kNominal;
+  const int64_t b0 = blocks(kNominal);
+  const int64_t rounds = std::max<int64_t>(1, (b0 + capacity / 2) / capacity);
+  const int64_t max_chunks = std::max<int64_t>(kXcd, (rounds * capacity / bpc) / kXcd * kXcd);
+  return std::max(kMin, (n_vis + max_chunks - 1) / max_chunks);
+}
+
 }  // namespace
 
 hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st) {
@@ -222,15 +255,20 @@ hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st) {
   ExtractArgs a = a0;
   a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);
   const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
-  const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
   const Sorted &v = a.sv;
   const uint64_t *wt = reinterpret_cast<const uint64_t *>(v.wt);
+  auto kmixed = k_extract<true, kNsMixed, kGroupMixed>;
+  auto kf64 = k_extract<false, kNsF64, kGroupF64>;
+  const int64_t capacity = mixed ? resident_blocks(kmixed, 1) : resident_blocks(kf64, 0);
+  a.chunk = (int32_t)chunk_size(v.n_vis, bpc, capacity);
+  a.n_chunks = (v.n_vis + a.chunk - 1) / a.chunk;
+  const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
   if (mixed)
-    hipLaunchKernelGGL((k_extract<true, kNsMixed, kGroupMixed>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a,
-                       v.geo, v.quad, v.res, wt, a.acc.cell);
+    hipLaunchKernelGGL(kmixed, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.geo, v.quad, v.res, wt,
+                       a.acc.cell);
   else
-    hipLaunchKernelGGL((k_extract<false, kNsF64, kGroupF64>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a,
-                       v.geo, v.quad, v.res, wt, a.acc.cell);
+    hipLaunchKernelGGL(kf64, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.geo, v.quad, v.res, wt,
+                       a.acc.cell);
   return hipGetLastError();
 }
 

@@ -22,7 +22,6 @@ constexpr double kArcsec = M_PI / 648000.0;     // radians per arcsecond
 constexpr double kC = 299792458.0;              // m/s
 constexpr int kVersion = 100;                   // 0.1.0
 constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
-constexpr int kExtractChunk = 2048;             // sorted visibilities per extraction wave
 constexpr int kSortedPad = 64;                  // zero-weight tail of the sorted arrays
 constexpr int kMaxRefineLevel = 12;             // finest refinement step e_step / 4096
 
@@ -699,8 +698,7 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
   a.n_chan = obs->n_chan;
   a.n_src = (int32_t)f->n_src;
   a.n_tiles = (int32_t)((f->n_src + 63) / 64);
-  a.chunk = kExtractChunk;
-  a.n_chunks = (f->sv.n_vis + kExtractChunk - 1) / kExtractChunk;
+  // chunk and n_chunks: chosen by the launcher from the device's occupancy
   a.chan = c->d_chan;
   a.src = f->d_src;
   a.src32 = f->d_src32;

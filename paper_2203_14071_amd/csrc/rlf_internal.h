@@ -99,7 +99,7 @@ struct ExtractArgs {
   int32_t n_chan;
   int32_t n_src;
   int32_t n_tiles;           // ceil(n_src / 64)
-  int32_t chunk;             // sorted visibilities per wave
+  int32_t chunk;             // sorted visibilities per wave (set by launch_extract)
   int64_t n_chunks;
   const ChanTable *chan;
   const SrcModel *src;

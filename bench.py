@@ -50,7 +50,7 @@ MODEL_FLOP_PAIR = 19
 # reading), for the kernel as it is now; None where not measured.
 # (profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md: fetch 1633.6 / 1219.1 MB,
 # write 6046.6 MB, nearly all of it the memory-side run-flush atomics)
-EXTRACT_TRAFFIC_BYTES = {"fp64": 8037.9e6, "mixed": 8469.4e6}
+EXTRACT_TRAFFIC_BYTES = {"fp64": 8015.3e6, "mixed": 8272.1e6}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Slots per unit of work count the method's necessary operations at their
 # measured gfx950 cost (FP64 and FP32 add/mul/FMA/round 1, v_sin/v_cos/v_rsq

@@ -2,6 +2,8 @@
 visibilities, 1000 sources, FP64) with the launch configuration the benchmark
 times.  The oracle checks sampled outputs it can compute one by one; the
 rest is checked through invariants that hold at any size."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -71,4 +73,42 @@ def test_extraction_and_fit_sampled_sources(field):
         G.check_facet(fac, s, ref, scale, cat.flux_jy[s])
         surf, est = oracle.fit_source(ref, cat.flux_jy[s])
         G.check_fit(h, s, surf, G.oracle_estimate_variants(surf), h["surface"][s])
+    f.free()
+
+
+def test_position_marginalised_fit_and_refinement_sampled_sources(field):
+    """The same field with the likelihood marginalised over a 3 x 3 offset
+    grid (0.2 arcsec) and then refined: sampled sources against the oracle's
+    fit_source_pos and refine_source on its own facets."""
+    from oracle.position import fit_source_pos
+    from oracle.refine import refine_source
+    cfg, o, cat, nz, obs, ctx = field
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    ctx.set_positions(f, 3, 0.2)
+    out = G.fit_out_tensors(cat.n_src)
+    ctx.fit_sources(f, out, want_surface=True)
+    ctx.sync()
+    h = G.host(out)
+    ctx.refine_sources(f, out)
+    ctx.sync()
+    hr = G.host(out)
+    a = cat.alpha_arcsec
+    for s in sorted({int(np.argmin(a)), 137}):
+        ref = G.oracle_facet(o, nz, cat, s)
+        surf, est = fit_source_pos(ref, cat.flux_jy[s], 3, 0.2)
+        G.check_fit(h, s, surf, G.oracle_estimate_variants(surf), h["surface"][s])
+        # refinement: compared where moving the threshold by a few LL_RTOL
+        # changes nothing (two correct FP64 evaluations may differ there)
+        p = oracle.Params()
+        d = 16 * G.LL_RTOL * max(1.0, abs(est.lmax))
+        runs = [refine_source(ref, cat.flux_jy[s], surf, est,
+                              dataclasses.replace(p, frac=p.frac * np.exp(x)), position=(3, 0.2))
+                for x in (0.0, -d, d)]
+        r = runs[0]
+        if int(h["n_above"][s]) == est.n_above and all(
+                q.n_above == r.n_above and q.flags == r.flags for q in runs[1:]):
+            assert int(hr["flags"][s]) == r.flags and int(hr["n_above"][s]) == r.n_above
+            for k in ("e1", "e2", "s1", "s2"):
+                assert abs(hr[k][s] - getattr(r, k)) <= G.E_TOL, (s, k)
     f.free()

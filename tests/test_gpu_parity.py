@@ -144,6 +144,42 @@ def test_all_flagged_gives_empty_facets(ctx):
     f.free()
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_single_visibility_single_source(ctx, fused):
+    """Smallest input: one row, one channel, one source (one extraction wave
+    and seven empty blocks of the XCD-rounded grid), through the explicit and
+    the library-computed residual: one cell, and the fit of that cell."""
+    g = np.random.default_rng(77)
+    o = synth.observation(0)
+    row = 1234
+    o1 = synth.Observation(o.u_m[row:row + 1].copy(), o.v_m[row:row + 1].copy(), o.w_m[row:row + 1].copy(),
+                           o.freq_hz.copy(), np.array([2.5e7]))
+    cat = synth.Catalogue(np.array([0.002]), np.array([-0.001]), np.array([80e-6]), np.array([1.2]),
+                          np.array([0.2]), np.array([-0.1]))
+    data = oracle.sky_model(o1.u_m, o1.v_m, o1.w_m, o1.freq_hz, cat) + (1e-5 + 2e-5j) * g.standard_normal(1)
+    catc = G.circular(cat)
+    obs = G.make_obs(o1, data)
+    f = ctx.facets_create(obs, catc)
+    if fused:
+        ctx.extract_facets(obs, catc, None, f)
+    else:
+        torch = G.torch_cuda()
+        res = torch.empty_like(obs.vis)
+        ctx.model_vis(obs, catc, res, mode=rlf.RLF_MODEL_RESIDUAL)
+        ctx.extract_facets(obs, catc, res, f)
+    out = G.fit_out_tensors(1)
+    ctx.fit_sources(f, out, want_surface=True)
+    ctx.sync()
+    fac, h = f.copy(), G.host(out)
+    resid = data - oracle.sky_model(o1.u_m, o1.v_m, o1.w_m, o1.freq_hz, catc)
+    ref = G.oracle_facet(o1, resid, catc, 0)
+    assert ref.n_cells == 1
+    G.check_facet(fac, 0, ref, float(np.max(np.abs(resid))), cat.flux_jy[0])
+    surf, _ = oracle.fit_source(ref, cat.flux_jy[0])
+    G.check_fit(h, 0, surf, G.oracle_estimate_variants(surf), h["surface"][0])
+    f.free()
+
+
 def test_repeat_extraction_is_self_cleaning(ctx):
     """A second extraction on the same facet object gives the same cells
     (the compaction step clears the accumulators)."""

@@ -209,6 +209,111 @@ def _evaluated_points(win, stride):
     return int(np.sum(box(cv, win)) + np.sum(int(lat.sum()) - box(cl, win)))
 
 
+def _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, full_frac, timed, outs, label, tag):
+    """Network-narrowed fits of facet object f against its full-grid fit `a`
+    (host arrays), one row per window half-width."""
+    from paper_2203_14071_amd import rlf, surrogate
+    n = cat.n_src
+    win = surrogate.Windowed(ctx, net, n)
+    t_feat = timed(lambda: (net.features(f, win.x), net.forward(win.x, win.y)))
+    rows = []
+    for ns in nsigmas:
+        nar = outs()
+        t_nar = timed(lambda: win.fit(f, nar, nsigma=ns, check_stride=check_stride, full_frac=full_frac))
+        b = {k: v.cpu().numpy() for k, v in nar.items()}
+        ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
+        de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
+        w = win.win.cpu().numpy()
+        area = (w[:, 1] - w[:, 0] + 1) * (w[:, 3] - w[:, 2] + 1)
+        refit = (b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0
+        evals = _evaluated_points(w, check_stride) + np.count_nonzero(refit) * 6333
+        y = win.y.cpu().numpy()
+        pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
+        rms = float(np.sqrt(np.mean(de ** 2)))
+        fb = float(np.mean(refit))
+        log(f"[bench] {label}, nsigma {ns}: narrowed fit {t_nar:.2f} ms (full {t_full:.2f} ms); RMS(de) {rms:.2e}; "
+            f"fallback {fb:.3f}; window {area.mean():.0f} points")
+        row = dict(tag)
+        row.update({"nsigma": ns, "check_stride": check_stride,
+                    "fit_ms": round(t_nar, 3), "of_which_features_and_network_ms": round(t_feat, 3),
+                    "fit_sources_per_s": round(n / (t_nar * 1e-3), 1),
+                    "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
+                    "fit_speedup_vs_plain": round(t_full / t_nar, 3),
+                    "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                    "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
+                    "mean_window_points": round(float(area.mean()), 1),
+                    "full_grid_windows": int(np.count_nonzero(area == 81 * 81)),
+                    "grid_points_evaluated_vs_full": round(evals / (6333 * n), 4),
+                    "network_rms_e_vs_true": round(pred_rms, 4)})
+        rows.append(row)
+    del win
+    return rows
+
+
+def narrowed_config1(params, steps, nsigmas, check_stride, full_frac):
+    """The benchmark's own field (config 1, FP64, 1000 sources): the step with
+    the full-grid fit against the step with the network-narrowed fit (network
+    trained on the config-1 population), the full grid judging the result."""
+    import torch
+
+    from paper_2203_14071_amd import rlf, synth
+
+    stream = torch.cuda.current_stream()
+    ctx = rlf.Context(0, stream.cuda_stream, rlf.params(precision=rlf.RLF_FP64))
+    cfg = synth.CONFIGS[1]
+    o = synth.observation(1)
+    cat = synth.catalogue(cfg, synth.rng(1, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(1, synth.STREAM_NOISE), o.n_rows * o.n_chan)
+    dev = "cuda:0"
+    t = lambda x, dt=None: torch.from_numpy(np.ascontiguousarray(x)).to(dev, dtype=dt)
+    obs = rlf.Obs(t(o.u_m), t(o.v_m), t(o.w_m), o.freq_hz, t(nz, torch.complex128), t(o.weight))
+    del nz
+    ctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
+    catc = cat.with_shape(np.zeros(cat.n_src), np.zeros(cat.n_src))
+    n = cat.n_src
+    f = ctx.facets_create(obs, catc)
+    resid = torch.empty_like(obs.vis)
+
+    def outs():
+        d = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("e1", "e2", "s1", "s2", "c12", "lmax")}
+        for k in ("argmax", "n_above", "flags"):
+            d[k] = torch.empty(n, dtype=torch.int32, device=dev)
+        return d
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_ext = timed(lambda: (ctx.model_vis(obs, catc, resid, mode=rlf.RLF_MODEL_RESIDUAL),
+                           ctx.extract_facets(obs, catc, resid, f)))
+    full = outs()
+    t_full = timed(lambda: ctx.fit_sources(f, full))
+    a = {k: v.cpu().numpy() for k, v in full.items()}
+    net = rlf.Mlp(ctx, 512)
+    net.set_state(params)
+    rows = _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, full_frac, timed, outs,
+                          "config 1 (FP64), config1 network", {"training_population": "config1"})
+    net.free()
+    f.free()
+    ctx.close()
+    del obs, resid
+    torch.cuda.empty_cache()
+    return {"workload": "ska_mid_1k (the benchmark's field), FP64: the step with the narrowed fit against the step "
+                        "with the full-grid fit",
+            "plain": {"model_and_extract_ms": round(t_ext, 3), "fit_ms": round(t_full, 3),
+                      "end_to_end_sources_per_s": round(n / ((t_ext + t_full) * 1e-3), 1),
+                      "posterior_sd_quantiles": {q: round(float(np.nanquantile(np.maximum(a["s1"], a["s2"]), q)), 4)
+                                                 for q in (0.1, 0.25, 0.5, 0.75, 0.9)}},
+            "narrowed": rows}
+
+
 def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, full_frac):
     """Config 3 (10,000 sources, 8 channels, mixed form): the captured batched
     pass, and the full-grid fit against the network-narrowed fit (network
@@ -273,6 +378,7 @@ def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, fu
     fit_rms = float(np.sqrt(np.nanmean((a["e1"] - cat.e1) ** 2 + (a["e2"] - cat.e2) ** 2) / 2))
     log(f"[bench] config 3: extract {t_ext:.2f} ms, full fit {t_full:.2f} ms")
     narrowed, training = [], []
+    config1_narrowed = None
     for pop in populations:
         net = rlf.Mlp(ctx, 512)
         net.set_state(surrogate.init_params())
@@ -286,37 +392,11 @@ def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, fu
         torch.cuda.empty_cache()
         training.append({"population": pop, "sources": n_train, "epochs": epochs, "simulate_s": round(t_sim, 2),
                          "train_s": round(t_train, 2), "loss_per_epoch": [round(h, 4) for h in hist]})
-        win = surrogate.Windowed(ctx, net, n)
-        t_feat = timed(lambda: (net.features(f, win.x), net.forward(win.x, win.y)))
-        for ns in nsigmas:
-            nar = outs()
-            t_nar = timed(lambda: win.fit(f, nar, nsigma=ns, check_stride=check_stride, full_frac=full_frac))
-            b = {k: v.cpu().numpy() for k, v in nar.items()}
-            ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
-            de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
-            w = win.win.cpu().numpy()
-            area = (w[:, 1] - w[:, 0] + 1) * (w[:, 3] - w[:, 2] + 1)
-            refit = (b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0
-            evals = _evaluated_points(w, check_stride) + np.count_nonzero(refit) * 6333
-            y = win.y.cpu().numpy()
-            pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
-            rms = float(np.sqrt(np.mean(de ** 2)))
-            fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
-            log(f"[bench] config 3, {pop} network, nsigma {ns}: narrowed fit {t_nar:.2f} ms "
-                f"(full {t_full:.2f} ms); RMS(de) {rms:.2e}; fallback {fb:.3f}; window {area.mean():.0f} points")
-            narrowed.append({"training_population": pop, "nsigma": ns, "check_stride": check_stride,
-                             "fit_ms": round(t_nar, 3), "of_which_features_and_network_ms": round(t_feat, 3),
-                             "fit_sources_per_s": round(n / (t_nar * 1e-3), 1),
-                             "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
-                             "fit_speedup_vs_plain": round(t_full / t_nar, 3),
-                             "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
-                             "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
-                             "mean_window_points": round(float(area.mean()), 1),
-                             "full_grid_windows": int(np.count_nonzero(area == 81 * 81)),
-                             "grid_points_evaluated_vs_full": round(evals / (6333 * n), 4),
-                             "network_rms_e_vs_true": round(pred_rms, 4)})
+        narrowed += _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, full_frac, timed,
+                                   outs, f"config 3, {pop} network", {"training_population": pop})
+        if pop == "config1":
+            config1_narrowed = narrowed_config1(net.get_state()["params"], steps, nsigmas, check_stride, full_frac)
         net.free()
-        del win
         torch.cuda.empty_cache()
 
     # the captured batched pass (residual + extraction + queue likelihood + estimate)
@@ -343,6 +423,7 @@ def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, fu
                   "posterior_sd_quantiles": {q: round(float(np.nanquantile(np.maximum(a["s1"], a["s2"]), q)), 4)
                                              for q in (0.1, 0.25, 0.5, 0.75, 0.9)}},
         "surrogate": narrowed,
+        "surrogate_on_config1_fp64": config1_narrowed,
         "training": training,
     }
     ctx.close()

@@ -40,7 +40,8 @@ from .extract import Facet, facet_theta, extract_facet, extract_facets
 from .likelihood import (alpha_knots, spline_quadrature_weights, log_normal_prior,
                          e_grid, loglike_alpha, marginal_surface, log_alpha_weights)
 from .estimate import Estimate, estimate, FLAG_BAD_VAR, FLAG_EMPTY, FLAG_EDGE, FLAG_FALLBACK
-from .fit import Params, fit_source, fit_sources, narrowed_fit, window_rejected
+from .fit import (Params, fit_source, fit_sources, narrowed_fit, window_rejected, lattice_window,
+                  lattice_narrowed_fit)
 from .sequential import FLAG_REFIT, SkyCatalogue, fit_sequential
 from .refine import FLAG_REFINED, refine_source
 from .position import offset_grid, loglike_alpha_offsets, marginal_surface_pos, fit_source_pos

@@ -106,6 +106,37 @@ def narrowed_fit(facet, flux_jy, window, check_stride=0, p: Params = Params(), m
     return full, dataclasses.replace(full_est, flags=full_est.flags | FLAG_FALLBACK), True
 
 
+def lattice_window(surface, check_stride, p: Params = Params()):
+    """Window seeded by a coarse lattice (not in the paper): from the values
+    of ln L(e) at the valid grid points whose offsets (i1 - c, i2 - c) from
+    the grid centre are both multiples of the stride S, the bounding box of
+    the lattice points within the 5 % threshold of the lattice maximum,
+    widened by S grid steps on every side and clamped to the grid
+    (i1lo, i1hi, i2lo, i2hi).  surface: flattened [n_e*n_e], read at the
+    lattice points only.  None when no lattice value is finite."""
+    i1, i2, _, _, valid = e_grid(p.n_e, p.e_step)
+    c = (p.n_e - 1) // 2
+    lat = valid & ((i1 - c) % check_stride == 0) & ((i2 - c) % check_stride == 0)
+    vals = np.where(lat, surface, -np.inf)
+    if not np.any(np.isfinite(vals)):
+        return None
+    member = lat & (vals >= np.max(vals) + math.log(p.frac))
+    return (max(int(i1[member].min()) - check_stride, 0), min(int(i1[member].max()) + check_stride, p.n_e - 1),
+            max(int(i2[member].min()) - check_stride, 0), min(int(i2[member].max()) + check_stride, p.n_e - 1))
+
+
+def lattice_narrowed_fit(facet, flux_jy, check_stride, p: Params = Params(), mu=None):
+    """The fit narrowed to the lattice-seeded window (lattice_window), with
+    the window rule and the full-grid fallback of narrowed_fit.  The lattice
+    values are those of the full surface (the same function at the same
+    points).  Returns (surface, estimate, refitted)."""
+    full, _ = fit_source(facet, flux_jy, p, mu)
+    window = lattice_window(full, check_stride, p)
+    if window is None:
+        window = (0, p.n_e - 1, 0, p.n_e - 1)
+    return narrowed_fit(facet, flux_jy, window, check_stride, p, mu)
+
+
 def fit_sources(facets, flux_jy, p: Params = Params(), mu=None):
     out = []
     for k, f in enumerate(facets):

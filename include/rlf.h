@@ -230,7 +230,16 @@ int rlf_facets_set_positions(rlf_ctx *ctx, rlf_facets *facets, int32_t n_side, d
 
 /* Fit options. */
 typedef struct {
-  int32_t mode;            /* 0 = full grid; 1 = windowed (window must be set)              */
+  int32_t mode;            /* 0 = full grid; 1 = windowed (window must be set); 2 = windowed on
+                              a window the library seeds from a lattice (not in the paper): ln L
+                              is first evaluated at the valid points whose offsets from the grid
+                              centre are multiples of check_stride (required, 2..n_e-1) on both
+                              axes, each source's window is the bounding box of those lattice
+                              points within the threshold of the lattice maximum widened by
+                              check_stride steps (clamped; the whole grid for an empty facet),
+                              and the fit proceeds as mode 1 with fallback and the lattice check
+                              (window and fallback are then ignored).  Not available on facets
+                              with position marginalisation (RLF_EUNSUPPORTED) nor in a pass.  */
   int32_t want_surface;    /* nonzero: write out->surface                                    */
   const int32_t *window;   /* device [n_src*4] inclusive (i1lo, i1hi, i2lo, i2hi) grid boxes */
   int32_t fallback;        /* windowed mode: nonzero = refit on the full grid (flag

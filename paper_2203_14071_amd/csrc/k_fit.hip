@@ -313,7 +313,9 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
 template <int R, bool kExact, bool kMixed>
 __global__ __launch_bounds__(256) void k_fit_window(FitArgs a, int num_r) {
   const int s = blockIdx.y;
-  int4 b = reinterpret_cast<const int4 *>(a.window)[s];
+  // lattice pass 1: the lattice alone (an empty box); pass 2: the lattice
+  // values are already in the surface, only the box is evaluated
+  int4 b = a.lattice_pass == 1 ? make_int4(1, 0, 1, 0) : reinterpret_cast<const int4 *>(a.window)[s];
   b.x = max(b.x, 0);                          // the box's part on the grid: at most n_e^2 positions
   b.y = min(b.y, a.n_e - 1);
   b.z = max(b.z, 0);
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(256) void k_fit_window(FitArgs a, int num_r) {
   const int area = (b.y >= b.x && b.w >= b.z) ? (b.y - b.x + 1) * w2 : 0;
   const int ctr = (a.n_e - 1) / 2;
   const int h = a.check_stride > 0 ? ctr / a.check_stride : 0;
-  const int nl = a.check_stride > 0 ? 2 * h + 1 : 0;
+  const int nl = (a.check_stride > 0 && a.lattice_pass != 2) ? 2 * h + 1 : 0;
   // a box with at least as many positions as the grid has valid points is
   // walked over the valid points instead (no idle lanes on |e| >= 1)
   const bool by_valid = area >= a.n_valid;
@@ -380,6 +382,53 @@ __global__ __launch_bounds__(256) void k_fit_queue(FitArgs a, QueueArgs q, int n
   }
 }
 
+// Window seeded by the stride-S lattice (after lattice pass 1): per source,
+// the bounding box of the lattice points within the threshold of the lattice
+// maximum, widened by S grid steps and clamped to the grid; the whole grid
+// for an empty facet.  One wave per source.
+__global__ __launch_bounds__(256) void k_lattice_windows(FitArgs a, double log_frac, int32_t *win) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= a.n_src) return;                                      // uniform per wave
+  int4 *w = reinterpret_cast<int4 *>(win) + s;
+  const int S = a.check_stride, ctr = (a.n_e - 1) / 2, h = ctr / S, nl = 2 * h + 1;
+  const double *L = a.lsurf + (int64_t)s * a.n_valid;
+  double best = -INFINITY;
+  if (a.offsets[s + 1] > a.offsets[s]) {
+    for (int u = lane; u < nl * nl; u += 64) {
+      const int j = a.valid_index[(ctr + S * (u / nl - h)) * a.n_e + ctr + S * (u % nl - h)];
+      if (j >= 0) best = fmax(best, L[j]);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) best = fmax(best, __shfl_xor(best, d));
+  if (!(best > -INFINITY)) {
+    if (lane == 0) *w = make_int4(0, a.n_e - 1, 0, a.n_e - 1);
+    return;
+  }
+  const double thr = best + log_frac;
+  int lo1 = a.n_e, hi1 = -1, lo2 = a.n_e, hi2 = -1;
+  for (int u = lane; u < nl * nl; u += 64) {
+    const int i1 = ctr + S * (u / nl - h), i2 = ctr + S * (u % nl - h);
+    const int j = a.valid_index[i1 * a.n_e + i2];
+    if (j >= 0 && L[j] >= thr) {
+      lo1 = min(lo1, i1);
+      hi1 = max(hi1, i1);
+      lo2 = min(lo2, i2);
+      hi2 = max(hi2, i2);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    lo1 = min(lo1, __shfl_xor(lo1, d));
+    hi1 = max(hi1, __shfl_xor(hi1, d));
+    lo2 = min(lo2, __shfl_xor(lo2, d));
+    hi2 = max(hi2, __shfl_xor(hi2, d));
+  }
+  if (lane == 0)
+    *w = make_int4(max(lo1 - S, 0), min(hi1 + S, a.n_e - 1), max(lo2 - S, 0), min(hi2 + S, a.n_e - 1));
+}
+
 __global__ void k_reset_counter(uint32_t *c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }
@@ -414,11 +463,12 @@ __global__ void k_reset_counter(uint32_t *c) {
 template <bool kMixed>
 hipError_t launch(const FitArgs &a, hipStream_t st) {
   if (a.n_pos) {
-    if (a.window) return hipErrorInvalidValue;          // full grid only
+    if (a.window || a.lattice_pass) return hipErrorInvalidValue;   // full grid only
     RLF_POS_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
-  } else if (a.window) {
+  } else if (a.window || a.lattice_pass == 1) {
     const int h = a.check_stride > 0 ? ((a.n_e - 1) / 2) / a.check_stride : 0;
-    const int positions = a.n_e * a.n_e + (a.check_stride > 0 ? (2 * h + 1) * (2 * h + 1) : 0);
+    const int lattice = (a.check_stride > 0 && a.lattice_pass != 2) ? (2 * h + 1) * (2 * h + 1) : 0;
+    const int positions = (a.lattice_pass == 1 ? 0 : a.n_e * a.n_e) + lattice;
     RLF_FIT_DISPATCH(k_fit_window, dim3((positions + 255) / 256, a.n_src), a);
   } else {
     RLF_FIT_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
@@ -464,6 +514,12 @@ hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, 
     else
       RLF_FIT_DISPATCH(k_refine_eval, grid, a, r);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice_windows(const FitArgs &a, double log_frac, int32_t *win, hipStream_t st) {
+  if (a.check_stride < 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lattice_windows, dim3((a.n_src + 3) / 4), dim3(256), 0, st, a, log_frac, win);
   return hipGetLastError();
 }
 

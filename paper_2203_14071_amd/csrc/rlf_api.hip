@@ -265,6 +265,7 @@ void free_facets(rlf_facets *f) {
   dfree(f->d_logw);
   dfree(f->d_lsurf);
   dfree(f->d_redo);
+  dfree(f->d_win);
   dfree(f->d_refine_win);
   dfree(f->d_refine_l);
   if (f->d_pos_g) (void)hipFree(f->d_pos_g);
@@ -604,6 +605,7 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     if ((rc = dalloc(c, &f->d_logw, f->n_src * R))) break;
     if ((rc = dalloc(c, &f->d_lsurf, f->n_src * (int64_t)c->n_valid))) break;
     if ((rc = dalloc(c, &f->d_redo, f->n_src))) break;
+    if ((rc = dalloc(c, &f->d_win, f->n_src * 4))) break;
   } while (0);
   if (rc != RLF_OK) {
     free_facets(f);
@@ -862,12 +864,15 @@ int rlf_fit_sources(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts *opts, r
   if (!out || !out->flags) return fail(c, RLF_EINVAL, "out/out.flags is NULL");
   rlf_fit_opts o{};
   if (opts) o = *opts;
-  if (o.check_stride != 0 && (o.mode != 1 || !o.fallback || o.check_stride < 2 || o.check_stride >= c->p.n_e))
+  if (o.mode != 0 && o.mode != 1 && o.mode != 2) return fail(c, RLF_EINVAL, "opts.mode");
+  if (o.mode == 2 && (o.check_stride < 2 || o.check_stride >= c->p.n_e))
+    return fail(c, RLF_EINVAL, "lattice-seeded mode needs opts.check_stride in 2..n_e-1");
+  if (o.mode != 2 && o.check_stride != 0 &&
+      (o.mode != 1 || !o.fallback || o.check_stride < 2 || o.check_stride >= c->p.n_e))
     return fail(c, RLF_EINVAL, "opts.check_stride: 0, or 2..n_e-1 in windowed mode with fallback");
-  if (o.mode != 0 && o.mode != 1) return fail(c, RLF_EINVAL, "opts.mode");
   if (o.mode == 1 && !o.window) return fail(c, RLF_EINVAL, "windowed mode needs opts.window");
   if (o.want_surface && !out->surface) return fail(c, RLF_EINVAL, "want_surface needs out.surface");
-  if (o.mode == 1 && f->pos_side > 1)
+  if (o.mode != 0 && f->pos_side > 1)
     return fail(c, RLF_EUNSUPPORTED, "position marginalisation is implemented for the full grid only");
   if (int e = set_device(c)) return e;
   return enqueue_fit(c, f, o, *out, nullptr, 0);
@@ -917,11 +922,23 @@ int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa) {
 
 int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rlf_fit_out &out,
                 const QueueArgs *queue, int queue_blocks) {
-  const bool windowed = o.mode == 1;
+  const bool lattice = o.mode == 2;
+  const bool windowed = o.mode == 1 || lattice;
   FitArgs fa{};
   if (int e = fit_args(c, f, fa)) return e;
-  fa.window = windowed ? o.window : nullptr;
-  fa.check_stride = (windowed && o.fallback) ? o.check_stride : 0;
+  if (lattice) {
+    // the stride-S lattice first, then each source's window from it
+    fa.check_stride = o.check_stride;
+    fa.lattice_pass = 1;
+    hipError_t e = f->mixed ? launch_fit_mixed(fa, c->stream) : launch_fit_f64(fa, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lattice pass launch");
+    e = launch_lattice_windows(fa, std::log(c->p.frac_thresh), f->d_win, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lattice window launch");
+    fa.lattice_pass = 2;
+  }
+  const bool fallback = lattice || o.fallback;
+  fa.window = lattice ? f->d_win : (windowed ? o.window : nullptr);
+  fa.check_stride = (windowed && fallback) ? o.check_stride : 0;
   fa.redo = nullptr;
   fa.lsurf = f->d_lsurf;
   EstimateArgs ea{};
@@ -938,7 +955,7 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   ea.lsurf = f->d_lsurf;
   ea.window = fa.window;
   ea.redo = nullptr;
-  ea.redo_out = (windowed && o.fallback) ? f->d_redo : nullptr;
+  ea.redo_out = (windowed && fallback) ? f->d_redo : nullptr;
   ea.check_stride = fa.check_stride;
   ea.e1 = out.e1;
   ea.e2 = out.e2;
@@ -958,9 +975,10 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   if (e != hipSuccess) return hip_fail(c, e, "fit kernel launch");
   e = launch_estimate(ea, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "estimate kernel launch");
-  if (windowed && o.fallback) {
+  if (windowed && fallback) {
     fa.window = nullptr;
     fa.check_stride = 0;
+    fa.lattice_pass = 0;
     fa.redo = f->d_redo;
     ea.window = nullptr;
     ea.check_stride = 0;

@@ -154,6 +154,9 @@ struct FitArgs {
   int32_t n_pos;
   const double *pos_g64;
   const float *pos_g32;
+  // lattice-seeded window: 1 = evaluate only the check_stride lattice (window
+  // ignored); 2 = the lattice values are already in lsurf (box only)
+  int32_t lattice_pass;
 };
 
 // Cross-correlation data of the position marginalisation (one row of n_pos
@@ -266,6 +269,7 @@ hipError_t launch_estimate(const EstimateArgs &a, hipStream_t st);
 hipError_t launch_absmax(const double *x, int64_t n, double *out2, int slot, hipStream_t st);
 hipError_t launch_refine_eval(const FitArgs &a, const RefineArgs &r, int mixed, hipStream_t st);
 hipError_t launch_pos_prep(const PosPrepArgs &a, int mixed, hipStream_t st);
+hipError_t launch_lattice_windows(const FitArgs &a, double log_frac, int32_t *win, hipStream_t st);
 hipError_t launch_refine_start(const RefineArgs &r, hipStream_t st);
 hipError_t launch_refine_estimate(const RefineArgs &r, hipStream_t st);
 hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t st);

@@ -62,6 +62,7 @@ struct rlf_facets {
   double *d_logw = nullptr;
   double *d_lsurf = nullptr;
   int32_t *d_redo = nullptr;
+  int32_t *d_win = nullptr;                  // lattice-seeded windows [n_src * 4]
   int32_t *d_refine_win = nullptr;           // refinement windows [n_src * 5] (made on first use)
   double *d_refine_l = nullptr;              // refinement window values [n_src * side^2]
   // position marginalisation (rlf_facets_set_positions): offsets per axis

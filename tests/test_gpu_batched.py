@@ -319,6 +319,73 @@ def test_window_rule_with_lattice_check_against_oracle(ctx):
     assert b[0] >= 35 and b[2] >= 2
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lattice_seeded_fit_against_oracle(precision):
+    """Mode 2 (the library seeds each window from a stride-4 lattice): the
+    windows, the fallback decisions and the kept or refitted results agree
+    with the oracle's lattice_narrowed_fit wherever moving the threshold by a
+    few LL_RTOL changes nothing; a low-noise and a nominal-noise field."""
+    mixed = precision == "mixed"
+    c = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64))
+    tol_e = 1e-4 if mixed else G.E_TOL
+    n_checked = n_kept = n_refit = 0
+    for noise_scale, seed in ((0.05, 81), (1.0, 83)):
+        cfg, o, cat, data = _field(n_src=40, seed=seed, noise_scale=noise_scale)
+        if mixed:
+            o.weight = o.weight.astype(np.float32).astype(np.float64)
+            data = data.astype(np.complex64).astype(np.complex128)
+        catc = G.circular(cat)
+        obs = G.make_obs(o, data.astype(np.complex64) if mixed else data, mixed=mixed)
+        f = c.facets_create(obs, catc)
+        c.extract_facets(obs, catc, None, f)
+        out = G.fit_out_tensors(cat.n_src, surface=False)
+        c.fit_sources(f, out, mode=2, check_stride=4)
+        c.sync()
+        h = G.host(out)
+        resid = data - oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, catc)
+        for s in range(cat.n_src):
+            fac = G.oracle_facet(o, resid, catc, s)
+            if fac.n_cells == 0:
+                assert h["flags"][s] & rlf.RLF_FLAG_EMPTY
+                continue
+            full, full_est = oracle.fit_source(fac, cat.flux_jy[s])
+            rel = (1e-5 if mixed else 3 * G.LL_RTOL) * max(1.0, abs(full_est.lmax)) * 4
+            wins = {oracle.lattice_window(full, 4, oracle.Params(frac=0.05 * math.exp(x))) for x in (0.0, -rel, rel)}
+            if len(wins) != 1:
+                continue
+            box = wins.pop()
+            surf_w, est_w = oracle.fit_source(fac, cat.flux_jy[s], window=box)
+            seen = full.copy()
+            seen[np.isfinite(surf_w)] = surf_w[np.isfinite(surf_w)]
+            if mixed:
+                d = 1e-5 * max(1.0, abs(est_w.lmax)) * 4
+                lo = oracle.window_rejected(seen, box, 4, oracle.Params(frac=0.05 * math.exp(-d)))
+                hi = oracle.window_rejected(seen, box, 4, oracle.Params(frac=0.05 * math.exp(+d)))
+                want = lo if lo == hi else None
+            else:
+                want = _robust_rejection(seen, box, 4, est_w.lmax)
+            if want is None:
+                continue
+            n_checked += 1
+            assert bool(h["flags"][s] & rlf.RLF_FLAG_FALLBACK) == want, (precision, seed, s, box)
+            ref = full_est if want else est_w
+            n_refit += want
+            n_kept += not want
+            if mixed:
+                assert abs(h["e1"][s] - ref.e1) <= tol_e and abs(h["e2"][s] - ref.e2) <= tol_e, (s, want)
+            elif want:
+                variants = G.oracle_estimate_variants(full)
+                for e in variants:
+                    e.flags |= rlf.RLF_FLAG_FALLBACK
+                G.check_fit(h, s, full, variants)
+            else:
+                G.check_fit(h, s, surf_w, G.oracle_estimate_variants(surf_w))
+        f.free()
+    print(f"lattice-seeded fit ({precision}): {n_checked} checked, {n_kept} kept, {n_refit} refitted")
+    assert n_checked >= 50 and n_kept >= 10
+    c.close()
+
+
 def test_check_stride_argument_errors(ctx):
     cfg, o, cat, data = _field(n_src=4, seed=71)
     obs = G.make_obs(o, data)
@@ -329,7 +396,9 @@ def test_check_stride_argument_errors(ctx):
                dict(mode=0, check_stride=4),                                  # needs a window
                dict(mode=1, window=win, fallback=True, check_stride=1),
                dict(mode=1, window=win, fallback=True, check_stride=81),
-               dict(mode=1, window=win, fallback=True, check_stride=-2)):
+               dict(mode=1, window=win, fallback=True, check_stride=-2),
+               dict(mode=2, check_stride=0), dict(mode=2, check_stride=1), dict(mode=2, check_stride=81),
+               dict(mode=3, check_stride=4)):
         with pytest.raises(rlf.RlfError):
             ctx.fit_sources(f, out, **kw)
     f.free()

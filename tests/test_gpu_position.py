@@ -189,6 +189,9 @@ def test_position_argument_errors_and_reset():
     with pytest.raises(rlf.RlfError) as e:
         ctx.fit_sources(f, G.fit_out_tensors(3), mode=1, window=win)
     assert e.value.code == rlf.RLF_EUNSUPPORTED
+    with pytest.raises(rlf.RlfError) as e:
+        ctx.fit_sources(f, G.fit_out_tensors(3), mode=2, check_stride=4)
+    assert e.value.code == rlf.RLF_EUNSUPPORTED
     # back to the fixed position: the same kernel as a facet object never set
     ctx.set_positions(f, 1)
     again = G.fit_out_tensors(3)

@@ -68,11 +68,26 @@ def test_extraction_and_fit_sampled_sources(field):
     a = cat.alpha_arcsec
     pick = sorted({int(np.argmin(a)), int(np.argmax(a)), int(np.argsort(a)[len(a) // 2]), 137})
     scale = np.max(np.abs(nz))
+    # the lattice-seeded window fit (stride 4) on the same facets
+    lat = G.fit_out_tensors(cat.n_src, surface=False)
+    ctx.fit_sources(f, lat, mode=2, check_stride=4)
+    ctx.sync()
+    hl = G.host(lat)
     for s in pick:
         ref = G.oracle_facet(o, nz, cat, s)
         G.check_facet(fac, s, ref, scale, cat.flux_jy[s])
         surf, est = oracle.fit_source(ref, cat.flux_jy[s])
         G.check_fit(h, s, surf, G.oracle_estimate_variants(surf), h["surface"][s])
+        d = 12 * G.LL_RTOL * max(1.0, abs(est.lmax))
+        wins = {oracle.lattice_window(surf, 4, oracle.Params(frac=0.05 * np.exp(x))) for x in (0.0, -d, d)}
+        if len(wins) == 1:
+            lsurf, _, refit = oracle.lattice_narrowed_fit(ref, cat.flux_jy[s], 4)
+            assert bool(hl["flags"][s] & rlf.RLF_FLAG_FALLBACK) == refit, s
+            variants = G.oracle_estimate_variants(lsurf)
+            if refit:
+                for e in variants:
+                    e.flags |= rlf.RLF_FLAG_FALLBACK
+            G.check_fit(hl, s, lsurf, variants)
     f.free()
 
 

@@ -151,7 +151,6 @@ def main():
 
     import torch
 
-    import oracle  # only for the cpu_baseline leg and the oracle's parameter defaults
 
     pops = [] if args.populations in ("", "none") else args.populations.split(",")
     if args.only_config3:
@@ -197,6 +196,7 @@ def main():
             "rows": rows, "s": round(time.perf_counter() - t0, 2)}
     if args.cpu_sample > 0:
         log(f"[bench] timing the oracle on {args.cpu_sample} sources")
+        import oracle  # the CPU-baseline leg only
         res["cpu_baseline"] = cpu_baseline(main_form["obs_host"], None, main_form["cat"], args.cpu_sample,
                                            oracle.Params())
     print(json.dumps(res), flush=True)

@@ -217,6 +217,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
     if (L[i].key != kNoRun && L[i].active) flush(acc, L[i], nproc);
 }
 
+// Visibility-parallel extraction for catalogues of at most kVpSources
+// sources (the chunks of a sequential refinement): a wave takes kVpSteps
+// steps of 64 consecutive sorted visibilities, one per lane (coalesced
+// loads), and evaluates each pair exactly as k_extract does (sources in a
+// uniform outer loop, records in SGPRs).  Lanes that fall in one facet cell
+// are contiguous runs of the sorted order, so a segmented scan over the
+// lanes sums each run; a run that reaches the last lane stays open (its
+// sums carried in registers) and continues into the next step, so a cell is
+// updated once per run of the sorted order (four FP64 atomics at one
+// address), as in k_extract.  A one-source call keeps every lane busy
+// instead of one lane in 128.
+constexpr int kVpSources = 8;
+constexpr int kVpSteps = 32;
+
+// Inclusive scan of x over the lanes of the same segment (segment ids are
+// non-decreasing along the lanes).
+__device__ __forceinline__ double seg_scan(double x, int seg, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_up(x, d);
+    const int os = __shfl_up(seg, d);
+    if (lane >= d && os == seg) x += o;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double lane63(double x) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+  return __hiloint2double(hi, lo);
+}
+
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4 *__restrict__ sgeo,
+                                                    const void *__restrict__ squad, const void *__restrict__ sres,
+                                                    const uint64_t *__restrict__ swt, double4 *__restrict__ acc) {
+  __shared__ double2 tab[kMixed ? 1 : kCisTable];
+  if (!kMixed) {
+    cis_table_init(tab);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63;
+  const int64_t jw = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kVpSteps);
+  if (jw >= a.sv.n_vis) return;                                  // uniform per wave
+  for (int s = 0; s < a.n_src; ++s) {                              // uniform
+    const SrcGeom g = a.geom[s];
+    const int64_t base = g.base + (int64_t)g.half * (g.side + 1);
+    const double half = (double)g.half, side = (double)g.side;
+    // the open run carried between steps (wave-uniform)
+    double ckey = kNoRun, cw = 0.0, cr = 0.0, ci = 0.0, cn = 0.0;
+    for (int t = 0; t < kVpSteps; ++t) {
+      const int64_t jb = jw + (int64_t)t * 64;
+      if (jb >= a.sv.n_vis) break;                               // uniform
+      const int64_t j = jb + lane;                               // < n_vis + 64: inside the padded arrays
+      const uint64_t wb = swt[j];
+      const bool use = j < a.sv.n_vis && wb != 0u;               // flagged and padding entries add nothing
+      const double ww = use ? __longlong_as_double((long long)wb) : 0.0;
+      const double4 gg = sgeo[j];
+      double zr, zi;
+      double xf, yf;
+      if (!kMixed) {
+        const double4 qg = reinterpret_cast<const double4 *>(squad)[j];
+        const double2 rg = reinterpret_cast<const double2 *>(sres)[j];
+        const SrcModel p = a.src[s];
+        const double ph = fma(gg.x, p.l, fma(gg.y, p.m, gg.z * p.n1));
+        const double2 cs = cis2pi_f64(ph, tab);
+        const double x = fma(p.q11, qg.x, fma(p.q12x2, qg.y, fma(p.q22, qg.z, 1.0)));
+        const double own = (kPowM32Scale * p.flux) * pow_m32_f64(x);
+        // w z = (w R) exp(-2 pi i ph) + (w spec) own
+        zr = fma(rg.x, cs.x, fma(rg.y, cs.y, qg.w * own));
+        zi = fma(rg.y, cs.x, -rg.x * cs.y);
+        xf = rint(__dmul_rn(gg.x, p.theta));
+        yf = rint(__dmul_rn(gg.y, p.theta));
+      } else {
+        const float4 qg = reinterpret_cast<const float4 *>(squad)[j];
+        const float2 rg = reinterpret_cast<const float2 *>(sres)[j];
+        const SrcMixed p = a.src32[s];
+        const double ph = fma(gg.x, p.l, fma(gg.y, p.m, gg.z * p.n1));
+        const float tt = (float)(ph - rint(ph));
+        const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
+        float fr = fmaf(rg.x, cs, rg.y * sn);
+        const float fi = fmaf(rg.y, cs, -(rg.x * sn));
+        const float x = fmaf(p.q11, qg.x, fmaf(p.q12x2, qg.y, fmaf(p.q22, qg.z, 1.0f)));
+        const float qr = __builtin_amdgcn_rsqf(x);
+        fr = fmaf(qg.w * p.flux, qr * qr * qr, fr);
+        zr = ww * (double)fr;
+        zi = ww * (double)fi;
+        xf = rint(__dmul_rn(gg.x, p.theta));
+        yf = rint(__dmul_rn(gg.y, p.theta));
+      }
+      const bool inb = fabs(xf) <= half && fabs(yf) <= half;
+      if (use && !inb) atomicOr(a.err, 1u);
+      const bool on = use && inb;
+      const double key = on ? fma(yf, side, xf) : kNoRun;
+      double vw = on ? ww : 0.0, vr = on ? zr : 0.0, vi = on ? zi : 0.0, vn = on ? 1.0 : 0.0;
+      // the carried run continues into lane 0's cell, or is closed now
+      if (ckey != kNoRun) {                                      // uniform
+        if (__shfl(key, 0) == ckey) {
+          if (lane == 0) {
+            vw += cw;
+            vr += cr;
+            vi += ci;
+            vn += cn;
+          }
+        } else if (lane == 0) {
+          double *c = &acc[base + (int32_t)ckey].x;
+          unsafeAtomicAdd(c, cw);
+          unsafeAtomicAdd(c + 1, cr);
+          unsafeAtomicAdd(c + 2, ci);
+          unsafeAtomicAdd(c + 3, cn);
+        }
+      }
+      // segments: runs of equal keys along the lanes
+      const double prev = __shfl_up(key, 1);
+      const bool head = lane == 0 || prev != key;
+      const int seg = __popcll(__ballot(head) & (((uint64_t)2 << lane) - 1));
+      vw = seg_scan(vw, seg, lane);
+      vr = seg_scan(vr, seg, lane);
+      vi = seg_scan(vi, seg, lane);
+      vn = seg_scan(vn, seg, lane);
+      const int next = __shfl_down(seg, 1);
+      if (lane < 63 && next != seg && on) {                      // a run that ends inside this step
+        double *c = &acc[base + (int32_t)key].x;
+        unsafeAtomicAdd(c, vw);
+        unsafeAtomicAdd(c + 1, vr);
+        unsafeAtomicAdd(c + 2, vi);
+        unsafeAtomicAdd(c + 3, vn);
+      }
+      // the run reaching lane 63 stays open
+      ckey = lane63(key);
+      cw = lane63(vw);
+      cr = lane63(vr);
+      ci = lane63(vi);
+      cn = lane63(vn);
+    }
+    if (ckey != kNoRun && lane == 0) {
+      double *c = &acc[base + (int32_t)ckey].x;
+      unsafeAtomicAdd(c, cw);
+      unsafeAtomicAdd(c + 1, cr);
+      unsafeAtomicAdd(c + 2, ci);
+      unsafeAtomicAdd(c + 3, cn);
+    }
+  }
+}
+
 // Resident blocks of an extraction kernel on the current device (cached).
 template <class K>
 int64_t resident_blocks(K kernel, int slot) {
@@ -253,10 +398,19 @@ int64_t chunk_size(int64_t n_vis, int64_t bpc, int64_t capacity) {
 hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st) {
   const int ns = mixed ? kNsMixed : kNsF64;
   ExtractArgs a = a0;
-  a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);
-  const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
   const Sorted &v = a.sv;
   const uint64_t *wt = reinterpret_cast<const uint64_t *>(v.wt);
+  if (a.n_src <= kVpSources) {
+    const int64_t waves = (v.n_vis + 64 * kVpSteps - 1) / (64 * kVpSteps);
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (mixed)
+      hipLaunchKernelGGL(k_extract_vp<true>, grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell);
+    else
+      hipLaunchKernelGGL(k_extract_vp<false>, grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell);
+    return hipGetLastError();
+  }
+  a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);
+  const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
   auto kmixed = k_extract<true, kNsMixed, kGroupMixed>;
   auto kf64 = k_extract<false, kNsF64, kGroupF64>;
   const int64_t capacity = mixed ? resident_blocks(kmixed, 1) : resident_blocks(kf64, 0);

@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--check-stride", type=int, default=4)
     ap.add_argument("--kscan", default="20,30,38,50,60,70,80,100",
                     help="facet-size factors K of the tuning experiment ('' or none = skip)")
-    ap.add_argument("--seq-chunks", default="1000,100,10",
+    ap.add_argument("--seq-chunks", default="1000,100,10,1",
                     help="chunk sizes of the sequential sky-model refinement to time ('' or none = skip)")
     ap.add_argument("--pos-sigma", default="0.1,0.3",
                     help="catalogue position errors (arcsec, per axis) of the position-marginalisation "

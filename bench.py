@@ -48,25 +48,24 @@ MODEL_FLOP_PAIR = 19
 # HBM bytes per launch of the dominant kernel (extraction) at this workload,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by a plain copy's
 # reading), for the kernel as it is now; None where not measured.
-# (profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md: fetch 1633.6 / 1219.1 MB,
-# write 6046.6 MB, nearly all of it the memory-side run-flush atomics)
-EXTRACT_TRAFFIC_BYTES = {"fp64": 8015.3e6, "mixed": 8272.1e6}
+EXTRACT_TRAFFIC_BYTES = {"fp64": None, "mixed": None}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
-# Slots per unit of work count the method's necessary operations at their
-# measured gfx950 cost (FP64 and FP32 add/mul/FMA/round 1, v_sin/v_cos/v_rsq
-# FP32 2, v_rsq FP64 4):
-#   extraction FP64 46 = phase 3, reduction + table sincos 15, rotation 4,
-#     profile (quadratic form 3, rsq 4 + correction 4, spec S 2) 13, index 6,
-#     run compare 1, accumulate 4;   mixed 36 = phase 3, reduction 3,
-#     sin + cos 4, rotation 4, profile 9, index 6, compare 1, accumulate 6
+# Slots per unit of work are the VALU instructions of the compiled hot loop
+# at their measured gfx950 cost (FP64 and FP32 add/mul/FMA/round and FP32
+# v_sin/v_cos/v_rsq 1, v_rsq FP64 4):
+#   extraction FP64 42 = phase 3, reduction 3, sincos polynomials + table
+#     index + rotation 12, profile (quadratic form 3, rsq 4, correction 4,
+#     flux 1) 12, cell index 4, run key + compare 2, run sums 6;
+#     mixed 31 (phase and reduction in FP64, v_sin/v_cos, FP32 rotation and
+#     profile, widening, FP64 run sums)
 #   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
-#     D 1, Mm 2;  mixed 8 = x 1, rsq 2, cube 2, D 1, Mm 2; plus 5 per
-#     (cell, point) shared by the knots
+#     D 1, Mm 2;  mixed 7 = x 1, rsq 1, cube 2, D 1, Mm 2; plus 5 per
+#     (cell, point) shared by the knots (mixed 10: two knot passes)
 #   sky-model DFT FP64 32 = phase 3, reduction + sincos 15, profile 3 + 8,
-#     amplitude 1, accumulate 2;  mixed 20 = phase 3, reduction 3, sin + cos 4,
-#     profile 3 + rsq 2 + cube 2, amplitude 1, accumulate 2
+#     amplitude 1, accumulate 2;  mixed 17 = phase 3, reduction 3, sin + cos 2,
+#     profile 3 + rsq 1 + cube 2, amplitude 1, accumulate 2
 SLOT_PEAK = 256 * 64 * 2.4e9
-SLOTS = {"fp64": {"extract": 44, "fit_knot": 12, "fit_point": 5, "model": 33},
+SLOTS = {"fp64": {"extract": 42, "fit_knot": 12, "fit_point": 5, "model": 32},
          "mixed": {"extract": 31, "fit_knot": 7, "fit_point": 10, "model": 17}}
 
 

@@ -4,13 +4,19 @@
 //
 // Work decomposition.  Lanes are sources: a wave holds 64 NS sources (NS per
 // lane, their constants in VGPRs; lane slots take the sources in order of
-// facet cell size, so the runs of a wave's lanes tend to end together and
-// the flushes diverge less) and walks a chunk of visibilities in the
+// facet cell size, so the cell changes of a wave's lanes tend to coincide
+// and the branches diverge less) and walks a chunk of visibilities in the
 // facet object's uv-sorted order; each visibility's data is uniform across
-// the wave and arrives through scalar loads.  Along the sorted order every
-// source stays in one facet cell for long runs, so each lane accumulates
-// (count, W, Z) in registers and issues global atomics only when its cell
-// changes or the chunk ends: no cross-lane merging is needed.
+// the wave and arrives through scalar loads.  Along the sorted order a
+// source stays in one facet cell for runs of ~100-300 visibilities and,
+// near a cell boundary, alternates between the same two cells many times
+// (a Morton curve crosses a boundary back and forth).  Each lane therefore
+// keeps two runs (count, W, Z) in registers, its current cell's and the
+// previous cell's, swaps them when it returns to the previous cell, and
+// issues global atomics only when it enters a third cell or the chunk ends:
+// on the 1000-source SKA-MID field one atomic flush per ~20 cell changes
+// (with one run per lane, every cell change flushed), and no cross-lane
+// merging is needed.
 //
 // XCD-aware launch: blocks are dispatched round-robin over the 8 XCDs; the
 // grid is laid out so that all blocks of one visibility chunk (all source
@@ -30,47 +36,75 @@ namespace {
 
 constexpr int kXcd = 8;
 constexpr int kWaves = 4;          // waves per block
-constexpr int kNsF64 = 2, kNsMixed = 2;        // sources per lane
+constexpr int kNsF64 = 1, kNsMixed = 1;        // sources per lane
 constexpr int kGroupF64 = 2, kGroupMixed = 4;  // visibilities whose scalar loads are issued together
 constexpr double kNoRun = 1099511627776.0;    // 2^40: "no open run" (run keys are below 2^31 in magnitude)
+constexpr int32_t kNoKey = INT32_MIN;          // the same for the previous run's integer key
 
-// One source of a lane: facet geometry and the open run.  The run key is
-// iy * side + ix (an exact integer in FP64); base already holds the offset
-// half * (side + 1) of cell (0, 0) in the source's dense block.  The run's
-// visibility count is the lane-independent count of processed visibilities
-// now minus its value when the run started.
+// One source of a lane: facet geometry and two open runs, the current cell's
+// and the cell the lane was in before it.  Near a cell boundary the sorted
+// order crosses back and forth between the same two cells many times, so a
+// return to the previous cell only swaps the two runs; global memory is
+// touched when a third cell is entered (the older run is flushed) and at
+// the end of the chunk.  A run key is iy * side + ix (an exact integer in
+// FP64); base already holds the offset half * (side + 1) of cell (0, 0) in
+// the source's dense block.  Counts are kept relative to the
+// lane-independent count nproc of processed visibilities: the current run
+// holds nproc - cb visibilities, the other run ocnt.
 struct LaneSrc {
   bool active;
+  int32_t half;
   int64_t base;
-  double half, side;
-  double key, rw, rzr, rzi;
-  int32_t start;
+  double side;
+  double key, rw, rzr, rzi;        // current cell
+  double ow, ozr, ozi;             // the cell before it
+  int32_t okey, cb, ocnt;          // okey: the previous cell's key, or kNoKey
 };
 
-// Add the open run to its dense cell: four FP64 atomics at one address (the
-// count is an exact integer in FP64).
-__device__ __forceinline__ void flush(double4 *__restrict__ acc, const LaneSrc &L, int32_t nproc) {
-  double *c = &acc[L.base + (int32_t)L.key].x;
-  unsafeAtomicAdd(c, L.rw);
-  unsafeAtomicAdd(c + 1, L.rzr);
-  unsafeAtomicAdd(c + 2, L.rzi);
-  unsafeAtomicAdd(c + 3, (double)(nproc - L.start));
+// Add a run to its dense cell: four FP64 atomics at one address (the count
+// is an exact integer in FP64).
+__device__ __forceinline__ void flush(double4 *__restrict__ acc, int64_t base, int32_t key, double w, double zr,
+                                      double zi, int32_t n) {
+  double *c = &acc[base + key].x;
+  unsafeAtomicAdd(c, w);
+  unsafeAtomicAdd(c + 1, zr);
+  unsafeAtomicAdd(c + 2, zi);
+  unsafeAtomicAdd(c + 3, (double)n);
 }
 
 // Run bookkeeping of one lane source at one visibility (nproc = visibilities
-// of the chunk with weight > 0 processed before this one, uniform): when the
-// cell changes, flush the open run and start a new one.  The caller then adds
-// the visibility's terms to the run sums.
+// of the chunk with weight > 0 processed before this one, uniform).  When
+// the cell changes: back to the previous cell swaps the two runs; a new cell
+// flushes the older run, demotes the current one and opens an empty run
+// (after the bounds check).  The caller then adds the visibility's terms to
+// the current run.
 __device__ __forceinline__ void enter_cell(LaneSrc &L, double4 *__restrict__ acc, uint32_t *err, int32_t nproc,
                                            double xf, double yf) {
   const double k = fma(yf, L.side, xf);
   if (k != L.key) {
-    if (L.key != kNoRun && L.active) flush(acc, L, nproc);
-    const bool inb = fabs(xf) <= L.half && fabs(yf) <= L.half;
-    if (!inb && L.active) atomicOr(err, 1u);
-    L.key = inb ? k : kNoRun;
-    L.start = nproc;
-    L.rw = L.rzr = L.rzi = 0.0;
+    const int32_t tk = L.key == kNoRun ? kNoKey : (int32_t)L.key;
+    const double tw = L.rw, tr = L.rzr, ti = L.rzi;
+    const int32_t tn = nproc - L.cb;
+    if (L.okey != kNoKey && k == (double)L.okey) {
+      L.key = (double)L.okey;
+      L.rw = L.ow;
+      L.rzr = L.ozr;
+      L.rzi = L.ozi;
+      L.cb = nproc - L.ocnt;
+    } else {
+      if (L.okey != kNoKey && L.active) flush(acc, L.base, L.okey, L.ow, L.ozr, L.ozi, L.ocnt);
+      const double half = (double)L.half;
+      const bool inb = fabs(xf) <= half && fabs(yf) <= half;
+      if (!inb && L.active) atomicOr(err, 1u);
+      L.key = inb ? k : kNoRun;
+      L.cb = nproc;
+      L.rw = L.rzr = L.rzi = 0.0;
+    }
+    L.okey = tk;
+    L.ow = tw;
+    L.ozr = tr;
+    L.ozi = ti;
+    L.ocnt = tn;
   }
 }
 
@@ -89,9 +123,13 @@ __device__ __forceinline__ void enter_cell(LaneSrc &L, double4 *__restrict__ acc
 // |key| < 2^31) and compared as a double, so the common path has no
 // conversions.  The facet half-size was sized on the host from the largest
 // |u|, |v| with the same rounding chain, so every index is inside its facet;
-// the bound is still checked whenever a run starts (err bit 0).
+// the bound is still checked whenever a new cell's run starts (err bit 0).
+//
+// Occupancy: the FP64 form is held to 64 VGPRs (eight waves per SIMD; only a
+// value live across the whole loop spills, outside it), the mixed form fits
+// eight waves by itself.
 template <bool kMixed, int NS, int G>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 : 5, 16))) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
+__global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
                                                  const void *__restrict__ squad, const void *__restrict__ sres,
                                                  const uint64_t *__restrict__ swt,
                                                  double4 *__restrict__ acc) {
@@ -117,11 +155,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
     src[i] = a.order[L[i].active ? s_raw : a.n_src - 1];
     const SrcGeom g = a.geom[src[i]];
     L[i].base = g.base + (int64_t)g.half * (g.side + 1);
-    L[i].half = (double)g.half;
+    L[i].half = g.half;
     L[i].side = (double)g.side;
     L[i].key = kNoRun;
-    L[i].start = 0;
+    L[i].okey = kNoKey;
+    L[i].cb = L[i].ocnt = 0;
     L[i].rw = L[i].rzr = L[i].rzi = 0.0;
+    L[i].ow = L[i].ozr = L[i].ozi = 0.0;
   }
   int32_t nproc = 0;
   const int64_t j0 = chunk * (int64_t)a.chunk;
@@ -150,6 +190,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
         rg[t] = res[jl + t];
         wwg[t] = wt[jl + t];
       }
+      // the group's values are needed here: the loads the compiler would
+      // otherwise sink past the weight test below (a second round trip to
+      // memory per group) are issued together with the others
+#pragma unroll
+      for (int t = 0; t < G; ++t)
+        asm volatile("" ::"s"(gg[t].x), "s"(gg[t].y), "s"(gg[t].z), "s"(qg[t].x), "s"(qg[t].y), "s"(qg[t].z));
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (jl + t >= len) break;                                   // uniform
@@ -188,6 +234,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
         rg[t] = res[jl + t];
         wwg[t] = wt[jl + t];
       }
+      // the group's values are needed here: the loads the compiler would
+      // otherwise sink past the weight test below (a second round trip to
+      // memory per group) are issued together with the others
+#pragma unroll
+      for (int t = 0; t < G; ++t)
+        asm volatile("" ::"s"(gg[t].x), "s"(gg[t].y), "s"(gg[t].z), "s"(qg[t].x), "s"(qg[t].y), "s"(qg[t].z));
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (jl + t >= len) break;                                   // uniform
@@ -213,8 +265,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMixed ? 6 
     }
   }
 #pragma unroll
-  for (int i = 0; i < NS; ++i)
-    if (L[i].key != kNoRun && L[i].active) flush(acc, L[i], nproc);
+  for (int i = 0; i < NS; ++i) {
+    if (!L[i].active) continue;
+    if (L[i].key != kNoRun) flush(acc, L[i].base, (int32_t)L[i].key, L[i].rw, L[i].rzr, L[i].rzi, nproc - L[i].cb);
+    if (L[i].okey != kNoKey) flush(acc, L[i].base, L[i].okey, L[i].ow, L[i].ozr, L[i].ozi, L[i].ocnt);
+  }
 }
 
 // Visibility-parallel extraction for catalogues of at most kVpSources

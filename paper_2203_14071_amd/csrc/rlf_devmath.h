@@ -7,10 +7,12 @@
 // [-1/2048, 1/2048] are exact, and k mod 1024 is the low ten bits of m's
 // mantissa.  Then exp(2 pi i phi) = T[k mod 1024] * exp(i x), x = 2 pi d,
 // with T[j] = exp(2 pi i j / 1024) from a 1024-entry table in LDS (16 KB),
-// and exp(i x), |x| <= pi/1024 < 3.1e-3, from its Taylor series: cos to x^4
-// (truncation < x^6/6! < 1.2e-18) and sin to x^5 (truncation
-// < x^7/7! < 4.3e-22).  About 15 VALU operations; the table index is in
-// range whatever phi is.
+// and exp(i x), x = 2 pi d, |x| <= pi/1024 < 3.1e-3, from its Taylor series
+// written in powers of d (the factors of 2 pi folded into the
+// coefficients): cos to x^4 (truncation < x^6/6! < 1.2e-18) and sin to x^5
+// (truncation < x^7/7! < 4.3e-22).  Fifteen VALU operations (two of them
+// form the table index) and one LDS read; the index is in range whatever
+// phi is.
 //
 // pow_m32_f64: (2/3) x^(-3/2) for x >= 1 from v_rsq_f64 (relative error
 // ~2^-24) with one correction: with y = rsq(x), x^(-3/2) = y^3 (1 + 3e/2 +
@@ -39,15 +41,29 @@ __device__ __forceinline__ void cis_table_init(double2 *tab) {
 
 constexpr double kTurnMagic = 6597069766656.0;   // 1.5 * 2^42: adding it rounds to 1/1024 turn
 
+// Taylor coefficients of cos(2 pi d) and sin(2 pi d) in powers of d (turns):
+// -(2 pi)^2 / 2, (2 pi)^4 / 24; 2 pi, -(2 pi)^3 / 6, (2 pi)^5 / 120.
+constexpr double kCos2 = -19.739208802178716, kCos4 = 64.9393940226683;
+constexpr double kSin1 = 6.283185307179586, kSin3 = -41.34170224039976, kSin5 = 81.60524927607506;
+
+// a * b + c as one VOP3 FMA with the addend c from an SGPR.  For an FMA
+// whose multiplier and addend are both constants the compiler keeps one of
+// them in a VGPR and copies it into the destination every time (a
+// two-address FMA); here the multiplier constant stays in a VGPR and the
+// addend is read as a scalar operand, one instruction instead of two.
+__device__ __forceinline__ double fma_vvs(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 // (cos 2 pi phi, sin 2 pi phi) with the table above.
 __device__ __forceinline__ double2 cis2pi_f64(double phi, const double2 *tab) {
   const double m = phi + kTurnMagic;
-  const double d = phi - (m - kTurnMagic);
-  const double x = d * 6.283185307179586476925286766559;
-  const double x2 = x * x;
-  // cos x = 1 - x^2/2 + x^4/24;  sin x = x (1 - x^2/6 + x^4/120)
-  const double cx = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0);
-  const double sx = x * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
+  const double d = phi - (m - kTurnMagic);       // turns, |d| <= 1/2048
+  const double d2 = d * d;
+  const double cx = fma(d2, fma_vvs(d2, kCos4, kCos2), 1.0);
+  const double sx = d * fma_vvs(d2, fma_vvs(d2, kSin5, kSin3), kSin1);
   const double2 tv = tab[(uint32_t)__double2loint(m) & (uint32_t)(kCisTable - 1)];
   return make_double2(fma(tv.x, cx, -(tv.y * sx)), fma(tv.x, sx, tv.y * cx));
 }

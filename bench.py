@@ -45,10 +45,16 @@ FIT_FLOP_CELL_POINT_KNOT = 10
 #     S f (MUL) 1, sum += amp (cos, sin) (2 FMA) 4                             = 19
 EXTRACT_FLOP_PAIR = 32
 MODEL_FLOP_PAIR = 19
-# HBM bytes per launch of the dominant kernel (extraction) at this workload,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by a plain copy's
-# reading), for the kernel as it is now; None where not measured.
-EXTRACT_TRAFFIC_BYTES = {"fp64": None, "mixed": None}
+# HBM bytes per timed stage (the kernels whose time the stage's HIP events
+# bracket) at this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (each
+# scaled by a plain copy's reading), for the kernels as they are now; None
+# where not measured.  profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md:
+#   extraction (k_extract): fetch 1688.9 / 1196.7 MB, write 1096.5 / 964.9 MB
+#   likelihood (k_fit + k_estimate): fetch 154.8 + 150.7 / 78.9 + 149.8 MB,
+#     write 51.3 + 0.3 / 51.3 + 0.3 MB
+#   sky model (k_model): fetch 372.9 / 298.3 MB, write 148.3 / 74.1 MB
+TRAFFIC_BYTES = {"fp64": {"extract": 2785.4e6, "fit": 357.1e6, "model": 521.2e6},
+                 "mixed": {"extract": 2161.6e6, "fit": 280.3e6, "model": 372.4e6}}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Slots per unit of work are the VALU instructions of the compiled hot loop
 # at their measured gfx950 cost (FP64 and FP32 add/mul/FMA/round and FP32
@@ -56,17 +62,18 @@ EXTRACT_TRAFFIC_BYTES = {"fp64": None, "mixed": None}
 #   extraction FP64 42 = phase 3, reduction 3, sincos polynomials + table
 #     index + rotation 12, profile (quadratic form 3, rsq 4, correction 4,
 #     flux 1) 12, cell index 4, run key + compare 2, run sums 6;
-#     mixed 31 (phase and reduction in FP64, v_sin/v_cos, FP32 rotation and
-#     profile, widening, FP64 run sums)
+#     mixed 30 (phase and fractional part in FP64, v_sin/v_cos, FP32
+#     rotation and profile, widening, FP64 run sums)
 #   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
 #     D 1, Mm 2;  mixed 7 = x 1, rsq 1, cube 2, D 1, Mm 2; plus 5 per
 #     (cell, point) shared by the knots (mixed 10: two knot passes)
 #   sky-model DFT FP64 32 = phase 3, reduction + sincos 15, profile 3 + 8,
-#     amplitude 1, accumulate 2;  mixed 17 = phase 3, reduction 3, sin + cos 2,
-#     profile 3 + rsq 1 + cube 2, amplitude 1, accumulate 2
+#     amplitude 1, accumulate 2;  mixed 16 = phase 3, fractional part and
+#     conversion 2, sin + cos 2, profile 3 + rsq 1 + cube 2, amplitude 1,
+#     accumulate 2
 SLOT_PEAK = 256 * 64 * 2.4e9
 SLOTS = {"fp64": {"extract": 42, "fit_knot": 12, "fit_point": 5, "model": 32},
-         "mixed": {"extract": 31, "fit_knot": 7, "fit_point": 10, "model": 17}}
+         "mixed": {"extract": 30, "fit_knot": 7, "fit_point": 10, "model": 16}}
 
 
 def log(*a):
@@ -629,8 +636,9 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
     }
     dominant = max(("extract", "fit", "model"), key=lambda k: {"model": stage_ms[0], "extract": stage_ms[1],
                                                                "fit": stage_ms[2]}[k])
+    for k in kernels:
+        kernels[k]["traffic"] = TRAFFIC_BYTES[precision][k]
     roofline = dict(kernels[dominant])
-    roofline["traffic"] = EXTRACT_TRAFFIC_BYTES[precision] if dominant == "extract" else None
     flags = out["flags"].cpu().numpy()
     e1 = out["e1"].cpu().numpy()
     e2 = out["e2"].cpu().numpy()

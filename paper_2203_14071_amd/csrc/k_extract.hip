@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
-          const float tt = (float)(ph - rint(ph));                   // turns, |t| <= 1/2
+          const float tt = (float)__builtin_amdgcn_fract(ph);        // turns, in [0, 1]
           const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
           float zr = fmaf(rg[t].x, cs, rg[t].y * sn);
           const float zi = fmaf(rg[t].y, cs, -(rg[t].x * sn));
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
         const float2 rg = reinterpret_cast<const float2 *>(sres)[j];
         const SrcMixed p = a.src32[s];
         const double ph = fma(gg.x, p.l, fma(gg.y, p.m, gg.z * p.n1));
-        const float tt = (float)(ph - rint(ph));
+        const float tt = (float)__builtin_amdgcn_fract(ph);
         const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
         float fr = fmaf(rg.x, cs, rg.y * sn);
         const float fi = fmaf(rg.y, cs, -(rg.x * sn));

@@ -8,8 +8,9 @@
 //               table + short polynomials (~15 ops), profile
 //               (3 FMA + corrected rsqrt cube, 5 ops, + 1 MUL), 2 FMA into the
 //               sum (the profile's constant 3/2 is applied once at the end);
-//   mixed form: phase and its reduction to [-1/2, 1/2] turns in FP64, then
-//               v_sin/v_cos (argument in turns), profile and sum in FP32.
+//   mixed form: phase and its fractional part (v_fract_f64, exact, in
+//               [0, 1) turns) in FP64, rounded to FP32 for v_sin/v_cos
+//               (argument in turns), profile and sum in FP32.
 // Two entry kernels: visibilities in caller order (rlf_model_vis), and the
 // residual in the facet object's uv-sorted order (extraction input).
 #include "rlf_devmath.h"
@@ -52,7 +53,7 @@ __device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const 
   float ar = 0.0f, ai = 0.0f;
   auto term = [&](const SrcMixed &p) {
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
-    const float t = (float)(ph - rint(ph));                 // turns, |t| <= 1/2
+    const float t = (float)__builtin_amdgcn_fract(ph);      // turns, in [0, 1]
     const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
     const float x = fmaf(p.q11, uu, fmaf(p.q12x2, uv, fmaf(p.q22, vv, 1.0f)));
     const float r = __builtin_amdgcn_rsqf(x);

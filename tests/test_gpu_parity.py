@@ -305,3 +305,71 @@ def test_facet_size_factor_matches_oracle(K):
         G.check_fit(out_g, s, surf_o, G.oracle_estimate_variants(surf_o, p), out_g["surface"][s])
     f.free()
     kctx.close()
+
+
+def _morton_changes(u, v, theta):
+    """Cell changes along a Z-order of the points (the test's own ordering, a
+    check that the input really alternates between cells)."""
+    def spread(x):
+        x = x & 0xffff
+        x = (x | (x << 8)) & 0x00ff00ff
+        x = (x | (x << 4)) & 0x0f0f0f0f
+        x = (x | (x << 2)) & 0x33333333
+        return (x | (x << 1)) & 0x55555555
+    q = lambda t: np.clip(np.floor((t / (2 * np.abs(t).max()) + 0.5) * 65536), 0, 65535).astype(np.int64)
+    order = np.argsort(spread(q(u)) | (spread(q(v)) << 1), kind="stable")
+    key = np.rint(v[order] * theta) * 1e6 + np.rint(u[order] * theta)
+    return int(np.count_nonzero(key[1:] != key[:-1])), int(np.unique(key).size)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_boundary_crossing_runs(precision):
+    """Visibilities packed densely around cell boundaries, so that along the
+    sorted order every source moves back and forth between neighbouring cells
+    many times (open runs swapped, older runs flushed on a third cell): 150
+    sources (three source tiles of the source-parallel kernel), cells and
+    counts bit-exact against the oracle, sums to rounding."""
+    mixed = precision == "mixed"
+    c = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64))
+    g = np.random.default_rng(2024)
+    n_src = 150
+    alpha = np.exp(g.normal(0.0, 0.3, n_src))
+    cat = synth.Catalogue(g.uniform(-2e-3, 2e-3, n_src), g.uniform(-2e-3, 2e-3, n_src),
+                          g.uniform(20e-6, 200e-6, n_src), alpha,
+                          g.uniform(-0.5, 0.5, n_src), g.uniform(-0.5, 0.5, n_src))
+    cell = 1.0 / np.median(oracle.facet_theta(alpha))               # median cell side in wavelengths
+    centres = g.uniform(-20 * cell, 20 * cell, (12, 2))
+    u = np.concatenate([cu + g.uniform(-cell, cell, 1500) for cu, _ in centres])
+    v = np.concatenate([cv + g.uniform(-cell, cell, 1500) for _, cv in centres])
+    n = u.size
+    w = g.uniform(-50.0, 50.0, n)
+    wt = g.uniform(0.5, 2.0, n)
+    wt[g.random(n) < 0.05] = 0.0                                     # flagged
+    resid = 1e-4 * (g.standard_normal(n) + 1j * g.standard_normal(n))
+    if mixed:
+        resid = resid.astype(np.complex64).astype(np.complex128)
+        wt = wt.astype(np.float32).astype(np.float64)
+    freq = np.array([synth.C_LIGHT])                                 # metres = wavelengths
+    changes, cells = _morton_changes(u, v, oracle.facet_theta(np.median(alpha)))
+    assert changes > 8 * cells                                        # the input does alternate
+    obs = rlf.Obs(G.to_dev(u), G.to_dev(v), G.to_dev(w), freq, G.complex_to_dev(resid, mixed),
+                  G.to_dev(wt.astype(np.float32) if mixed else wt))
+    f = c.facets_create(obs, cat)
+    c.extract_facets(obs, cat, obs.vis, f)
+    fac = f.copy()
+    scale = float(np.max(np.abs(resid)))
+    for s in range(n_src):
+        theta = oracle.facet_theta(cat.alpha_arcsec[s])
+        src = (cat.l[s], cat.m[s], cat.flux_jy[s], cat.alpha_arcsec[s], cat.e1[s], cat.e2[s])
+        ref = oracle.extract_facet(u, v, w, freq, wt, resid, src, theta)
+        if not mixed:
+            G.check_facet(fac, s, ref, scale, cat.flux_jy[s])
+            continue
+        a, b = int(fac["offsets"][s]), int(fac["offsets"][s + 1])
+        assert b - a == ref.n_cells, s
+        for key in ("ix", "iy", "count"):
+            assert np.array_equal(fac[key][a:b], getattr(ref, key)), (s, key)
+        assert np.allclose(fac["wsum"][a:b], ref.wsum, rtol=1e-12), s
+        assert np.max(np.abs(fac["vbar"][a:b] - ref.vbar)) <= 2e-5 * (scale + cat.flux_jy[s]), s
+    f.free()
+    c.close()

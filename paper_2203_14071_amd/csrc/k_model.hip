@@ -155,6 +155,7 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
     // factor in the fourth slot of the quadratic terms
     reinterpret_cast<double2 *>(a.sv.res)[j] = make_double2(wpos * r.x, wpos * r.y);
     reinterpret_cast<double4 *>(a.sv.quad)[j].w = wpos * g.w;
+    if (a.rs) a.rs[j] = r;
   } else {
     float2 r = reinterpret_cast<const float2 *>(a.vis)[i];
     if (a.subtract) {
@@ -168,7 +169,52 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
   a.sv.wt[j] = wpos;
 }
 
+// Residual kept in sorted order, updated for changed source models: the
+// old models' sum is added and the new models' sum subtracted with the
+// arithmetic of k_model's accumulate and residual modes, so the result is
+// the one those two passes and a gather would give.
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_update_sorted(UpdateArgs a) {
+  __shared__ double2 tab[kMixed ? 1 : kCisTable];
+  if (!kMixed) {
+    cis_table_init(tab);
+    __syncthreads();
+  }
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.sv.n_vis) return;
+  const double4 g = a.sv.geo[j];
+  if (!kMixed) {
+    const double2 ao = sum_f64(g.x, g.y, g.z, a.old64, 0, a.n_old, tab);
+    const double2 an = sum_f64(g.x, g.y, g.z, a.new64, 0, a.n_new, tab);
+    double2 r = a.rs[j];
+    r = make_double2(fma(g.w, ao.x, r.x), fma(g.w, ao.y, r.y));
+    r = make_double2(fma(-g.w, an.x, r.x), fma(-g.w, an.y, r.y));
+    a.rs[j] = r;
+    const double wpos = a.sv.wt[j];
+    reinterpret_cast<double2 *>(a.sv.res)[j] = make_double2(wpos * r.x, wpos * r.y);
+  } else {
+    const float2 ao = sum_mixed(g.x, g.y, g.z, a.old32, 0, a.n_old);
+    const float2 an = sum_mixed(g.x, g.y, g.z, a.new32, 0, a.n_new);
+    const float sp = (float)g.w;
+    float2 *res = reinterpret_cast<float2 *>(a.sv.res);
+    float2 r = res[j];
+    r = make_float2(fmaf(sp, ao.x, r.x), fmaf(sp, ao.y, r.y));
+    r = make_float2(fmaf(-sp, an.x, r.x), fmaf(-sp, an.y, r.y));
+    res[j] = r;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_update_sorted(const UpdateArgs &a, int mixed, hipStream_t st) {
+  const int64_t blocks = (a.sv.n_vis + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(k_update_sorted<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_update_sorted<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st) {
   const int64_t n = a.n_rows * a.n_chan;

@@ -655,23 +655,13 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
   return RLF_OK;
 }
 
-}  // namespace rlf
-
-extern "C" {
-
-int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets **out) {
-  if (!c) return RLF_EINVAL;
-  c->err.clear();
-  return create_facets(c, obs, cat, nullptr, out);
-}
-
-int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *residual,
-                       rlf_facets *f) {
-  if (!c) return RLF_EINVAL;
-  c->err.clear();
+// Gather (or subtract the facet object's own catalogue from) the visibilities
+// into the sorted layout, then extract and compact; `vis` NULL: the sorted
+// layout already holds the residual (kept there by the caller), no gather.
+int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *vis, int subtract,
+                   rlf_facets *f) {
   if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
   if (int e = check_obs(c, obs)) return e;
-  if (!residual && !obs->vis) return fail(c, RLF_EINVAL, "residual and obs.vis are both NULL");
   if (obs->n_rows * obs->n_chan != f->sv.n_vis) return fail(c, RLF_EINVAL, "observation size differs from rlf_facets_create");
   if (int e = check_cat(c, cat, false)) return e;
   if (cat->n_src != f->n_src || std::memcmp(cat->alpha_arcsec, f->alpha.data(), sizeof(double) * f->n_src) != 0)
@@ -683,18 +673,21 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
     if (int e = upload_sources(c, cat, f->d_src, f->d_src32)) return e;
     f->model_key.swap(key);
   }
-  ResidualArgs ra{};
-  ra.sv = f->sv;
-  ra.n_chan = obs->n_chan;
-  ra.n_src = (int32_t)f->n_src;
-  ra.chan = c->d_chan;
-  ra.src = f->d_src;
-  ra.src32 = f->d_src32;
-  ra.vis = residual ? residual : obs->vis;
-  ra.weight = obs->weight;
-  ra.subtract = residual ? 0 : 1;
-  hipError_t e = launch_residual_sorted(ra, f->mixed, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "residual kernel launch");
+  hipError_t e = hipSuccess;
+  if (vis) {
+    ResidualArgs ra{};
+    ra.sv = f->sv;
+    ra.n_chan = obs->n_chan;
+    ra.n_src = (int32_t)f->n_src;
+    ra.chan = c->d_chan;
+    ra.src = f->d_src;
+    ra.src32 = f->d_src32;
+    ra.vis = vis;
+    ra.weight = obs->weight;
+    ra.subtract = subtract;
+    e = launch_residual_sorted(ra, f->mixed, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "residual kernel launch");
+  }
   ExtractArgs a{};
   a.sv = f->sv;
   a.n_chan = obs->n_chan;
@@ -719,6 +712,77 @@ int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, c
   e = launch_compact(ca, f->mixed, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "compact kernel launch");
   return RLF_OK;
+}
+
+// Residual of the sky catalogue `sky` (obs.vis minus its models) into the
+// sorted layout of f, with the unweighted FP64 residual in `rs` as well.
+int sorted_residual(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *sky, const rlf_facets *f, double2 *rs) {
+  if (int e = check_obs(c, obs)) return e;
+  if (!obs->vis) return fail(c, RLF_EINVAL, "obs.vis is NULL");
+  if (obs->n_rows * obs->n_chan != f->sv.n_vis) return fail(c, RLF_EINVAL, "observation size differs");
+  if (int e = check_cat(c, sky, false)) return e;
+  if (!f->mixed && !rs) return fail(c, RLF_EINVAL, "FP64 form needs the unweighted residual buffer");
+  if (int e = set_device(c)) return e;
+  if (int e = chan_table(c, obs)) return e;
+  const SrcModel *d_src = nullptr;
+  const SrcMixed *d_src32 = nullptr;
+  if (int e = model_table(c, sky, &d_src, &d_src32)) return e;
+  ResidualArgs ra{};
+  ra.sv = f->sv;
+  ra.n_chan = obs->n_chan;
+  ra.n_src = (int32_t)sky->n_src;
+  ra.chan = c->d_chan;
+  ra.src = d_src;
+  ra.src32 = d_src32;
+  ra.vis = obs->vis;
+  ra.weight = obs->weight;
+  ra.subtract = 1;
+  ra.rs = f->mixed ? nullptr : rs;
+  hipError_t e = launch_residual_sorted(ra, f->mixed, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "residual kernel launch");
+  return RLF_OK;
+}
+
+// R += (models of old_m) - (models of new_m) on the residual kept in the
+// sorted layout of f (and in rs for the FP64 form).
+int update_sorted_residual(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
+                           double2 *rs) {
+  if (int e = check_cat(c, old_m, false)) return e;
+  if (int e = check_cat(c, new_m, false)) return e;
+  if (!f->mixed && !rs) return fail(c, RLF_EINVAL, "FP64 form needs the unweighted residual buffer");
+  if (int e = set_device(c)) return e;
+  UpdateArgs u{};
+  // the two tables sit in the context's two model slots: the second lookup
+  // replaces the least recently used slot, never the one just returned
+  if (int e = model_table(c, old_m, &u.old64, &u.old32)) return e;
+  if (int e = model_table(c, new_m, &u.new64, &u.new32)) return e;
+  if (u.old64 == u.new64 && cat_key(old_m) != cat_key(new_m))
+    return fail(c, RLF_EINVAL, "model tables of the update share a slot");
+  u.sv = f->sv;
+  u.n_old = (int32_t)old_m->n_src;
+  u.n_new = (int32_t)new_m->n_src;
+  u.rs = f->mixed ? nullptr : rs;
+  hipError_t e = launch_update_sorted(u, f->mixed, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "residual update kernel launch");
+  return RLF_OK;
+}
+
+}  // namespace rlf
+
+extern "C" {
+
+int rlf_facets_create(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets **out) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  return create_facets(c, obs, cat, nullptr, out);
+}
+
+int rlf_extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *residual,
+                       rlf_facets *f) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (!residual && (!obs || !obs->vis)) return fail(c, RLF_EINVAL, "residual and obs.vis are both NULL");
+  return extract_facets(c, obs, cat, residual ? residual : obs->vis, residual ? 0 : 1, f);
 }
 
 int rlf_facets_info(rlf_ctx *c, const rlf_facets *f, int64_t *n_src, int64_t *n_cells, int64_t *n_dense) {

@@ -122,6 +122,20 @@ struct ResidualArgs {
   const void *vis;           // caller order
   const void *weight;        // caller order
   int32_t subtract;          // 1: vis - sky; 0: gather only
+  double2 *rs;               // optional, FP64 form: the unweighted residual R in sorted order
+};
+
+// In-place update of a residual kept in sorted order when some sources'
+// models change: R += sum over old models - sum over new models (Eq. 1),
+// evaluated and added as rlf_model_vis would (old ones accumulated, then the
+// new ones subtracted).  FP64 form: R in rs, and sv.res = w R rewritten;
+// mixed form: sv.res holds R itself.
+struct UpdateArgs {
+  Sorted sv;
+  int32_t n_old, n_new;
+  const SrcModel *old64, *new64;
+  const SrcMixed *old32, *new32;
+  double2 *rs;
 };
 
 struct CompactArgs {
@@ -255,6 +269,7 @@ struct FeatureArgs {
 hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st);
 hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st);
 hipError_t launch_residual_sorted(const ResidualArgs &a, int mixed, hipStream_t st);
+hipError_t launch_update_sorted(const UpdateArgs &a, int mixed, hipStream_t st);
 hipError_t launch_sort_keys(const SortKeyArgs &a, hipStream_t st);
 hipError_t sort_pairs_u32(void *tmp, size_t &tmp_bytes, const uint32_t *kin, uint32_t *kout, const uint32_t *vin,
                           uint32_t *vout, int64_t n, hipStream_t st);

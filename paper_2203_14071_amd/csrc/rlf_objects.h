@@ -117,4 +117,17 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
 // included); enqueues the cross-correlation data when offsets are set.
 int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa);
 
+// Extraction into f: with `vis`, first the gather into f's sorted layout
+// (subtract = 1: minus f's own catalogue models); with vis NULL the sorted
+// layout already holds the residual.
+int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *vis, int subtract,
+                   rlf_facets *f);
+
+// A residual kept in the sorted layout of f (sequential refinement): set it
+// to obs.vis minus the models of `sky`, then update it as models change.
+// FP64 form: rs [n_vis] holds the unweighted residual next to sv.res = w R.
+int sorted_residual(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *sky, const rlf_facets *f, double2 *rs);
+int update_sorted_residual(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
+                           double2 *rs);
+
 }  // namespace rlf

@@ -2,11 +2,15 @@
 // the sky model starts circular and each measured shape replaces the
 // model's; Sec. 2.4: unreliable fits keep their model and are fitted again at
 // the end; Sec. 3.1: with several sources fitted at once the model is updated
-// per chunk).  The host orders the chunks; every step on the visibilities is
-// an existing kernel: the residual DFT, the extraction into a facet object
-// that borrows the first chunk's uv-sorted layout, the full-grid fit, and the
-// in-place residual update R += (old models) - (new models) of the refined
-// sources.
+// per chunk).  The host orders the chunks.  The residual lives in the
+// uv-sorted layout of the first chunk's facet object, which every later
+// chunk borrows: it is formed once (the residual DFT of the whole starting
+// model, in sorted order), each chunk is extracted from it directly (no
+// gather) and fitted on the full grid, and the refined sources' models are
+// then swapped in place, R += (old models) - (new models), in one pass over
+// the sorted visibilities.  The arithmetic is that of the caller-order path
+// (rlf_model_vis residual, accumulate and residual modes, then a gather), so
+// the results are the same.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,15 +105,14 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
   std::vector<double> e1(cat->e1, cat->e1 + n), e2(cat->e2, cat->e2 + n);
   Scratch sc;
 
-  // residual of the starting model, kept in place from here on
-  double *R = nullptr;
-  if (int e = sc.alloc(c, &R, n_vis * (mixed ? 1 : 2))) return e;
+  // FP64 form: the unweighted residual next to the weighted one the
+  // extraction reads (the mixed form keeps R itself in the sorted layout)
+  double2 *Rs = nullptr;
+  if (!mixed)
+    if (int e = sc.alloc(c, &Rs, n_vis)) return e;
   rlf_catalog cur = *cat;
   cur.e1 = e1.data();
   cur.e2 = e2.data();
-  if (int e = rlf_model_vis(c, obs, &cur, 0, n, R, RLF_MODEL_RESIDUAL)) return e;
-  rlf_obs ro = *obs;
-  ro.vis = R;
 
   rlf_fit_opts full{};
   std::vector<uint32_t> flags((size_t)n, 0u);
@@ -124,8 +127,12 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
     rlf_facets *f = nullptr;
     if (int e = create_facets(c, obs, &v, master, &f)) return e;
     sc.facets.push_back(f);
-    if (!master) master = f;
-    if (int e = rlf_extract_facets(c, obs, &v, R, f)) return e;
+    if (!master) {
+      // residual of the starting model, kept in place from here on
+      master = f;
+      if (int e = sorted_residual(c, obs, &cur, master, Rs)) return e;
+    }
+    if (int e = extract_facets(c, obs, &v, nullptr, 0, f)) return e;
     rlf_fit_out o = offset(*out, c0);
     if (int e = rlf_fit_sources(c, f, &full, &o)) return e;
     const size_t m = (size_t)(c1 - c0);
@@ -151,8 +158,7 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
       }
       const SubCat new_m = subset(cat, good, e1, e2);
       const rlf_catalog vo = old_m.view(), vn = new_m.view();
-      if (int e = rlf_model_vis(c, &ro, &vo, 0, vo.n_src, R, RLF_MODEL_ACCUMULATE)) return e;
-      if (int e = rlf_model_vis(c, &ro, &vn, 0, vn.n_src, R, RLF_MODEL_RESIDUAL)) return e;
+      if (int e = update_sorted_residual(c, &vo, &vn, master, Rs)) return e;
     }
   }
 
@@ -167,7 +173,7 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
       rlf_facets *f = nullptr;
       if (int e = create_facets(c, obs, &v, master, &f)) return e;
       sc.facets.push_back(f);
-      if (int e = rlf_extract_facets(c, obs, &v, R, f)) return e;
+      if (int e = extract_facets(c, obs, &v, nullptr, 0, f)) return e;
       double *t[6];
       int32_t *ti[2], *tidx = nullptr;
       uint32_t *tf = nullptr;

@@ -286,21 +286,57 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
 constexpr int kVpSources = 8;
 constexpr int kVpSteps = 32;
 
-// Inclusive scan of x over the lanes of the same segment (segment ids are
-// non-decreasing along the lanes).
-__device__ __forceinline__ double seg_scan(double x, int seg, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double o = __shfl_up(x, d);
-    const int os = __shfl_up(seg, d);
-    if (lane >= d && os == seg) x += o;
+// Cross-lane moves by DPP (a VALU operand modifier: no LDS round trip).
+// Lanes whose source is outside the pattern, or whose row is masked out,
+// receive `old`.
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ int dpp(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, kCtrl, kRowMask, 0xf, false);
+}
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ double dpp(double old, double v) {
+  return __hiloint2double(dpp<kCtrl, kRowMask>(__double2hiint(old), __double2hiint(v)),
+                          dpp<kCtrl, kRowMask>(__double2loint(old), __double2loint(v)));
+}
+constexpr int kRowShr = 0x110;      // + n: row_shr:n (within rows of 16 lanes)
+constexpr int kRowBcast15 = 0x142;  // lane 15 of a row to the whole next row
+constexpr int kRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+constexpr int kWaveShr1 = 0x138;    // lane i - 1 to lane i across the wave
+constexpr int kWaveShl1 = 0x130;    // lane i + 1 to lane i across the wave
+
+// One level of the segmented scan: add the value `kCtrl` brings in when it
+// comes from the same segment.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_level(double &a, double &b, double &c, double &d, int seg) {
+  const bool take = dpp<kCtrl, kRowMask>(-1, seg) == seg;        // segment ids are >= 1
+  const double oa = dpp<kCtrl, kRowMask>(0.0, a), ob = dpp<kCtrl, kRowMask>(0.0, b);
+  const double oc = dpp<kCtrl, kRowMask>(0.0, c), od = dpp<kCtrl, kRowMask>(0.0, d);
+  if (take) {
+    a += oa;
+    b += ob;
+    c += oc;
+    d += od;
   }
-  return x;
 }
 
-__device__ __forceinline__ double lane63(double x) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+// Inclusive scans of a, b, c, d over the lanes of the same segment (segment
+// ids non-decreasing along the lanes, >= 1): shifts by 1, 2, 4 and 8 within
+// rows of 16 lanes, then row 0's last lane into row 1 and row 2's into row
+// 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ void seg_scan4(double &a, double &b, double &c, double &d, int seg) {
+  seg_level<kRowShr + 1, 0xf>(a, b, c, d, seg);
+  seg_level<kRowShr + 2, 0xf>(a, b, c, d, seg);
+  seg_level<kRowShr + 4, 0xf>(a, b, c, d, seg);
+  seg_level<kRowShr + 8, 0xf>(a, b, c, d, seg);
+  seg_level<kRowBcast15, 0xa>(a, b, c, d, seg);
+  seg_level<kRowBcast31, 0xc>(a, b, c, d, seg);
+}
+
+// The value of lane L (wave-uniform).
+template <int L>
+__device__ __forceinline__ double read_lane(double x) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), L);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), L);
   return __hiloint2double(hi, lo);
 }
 
@@ -369,7 +405,7 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
       double vw = on ? ww : 0.0, vr = on ? zr : 0.0, vi = on ? zi : 0.0, vn = on ? 1.0 : 0.0;
       // the carried run continues into lane 0's cell, or is closed now
       if (ckey != kNoRun) {                                      // uniform
-        if (__shfl(key, 0) == ckey) {
+        if (read_lane<0>(key) == ckey) {
           if (lane == 0) {
             vw += cw;
             vr += cr;
@@ -385,14 +421,11 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
         }
       }
       // segments: runs of equal keys along the lanes
-      const double prev = __shfl_up(key, 1);
+      const double prev = dpp<kWaveShr1>(key, key);
       const bool head = lane == 0 || prev != key;
       const int seg = __popcll(__ballot(head) & (((uint64_t)2 << lane) - 1));
-      vw = seg_scan(vw, seg, lane);
-      vr = seg_scan(vr, seg, lane);
-      vi = seg_scan(vi, seg, lane);
-      vn = seg_scan(vn, seg, lane);
-      const int next = __shfl_down(seg, 1);
+      seg_scan4(vw, vr, vi, vn, seg);
+      const int next = dpp<kWaveShl1>(-1, seg);
       if (lane < 63 && next != seg && on) {                      // a run that ends inside this step
         double *c = &acc[base + (int32_t)key].x;
         unsafeAtomicAdd(c, vw);
@@ -401,11 +434,11 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
         unsafeAtomicAdd(c + 3, vn);
       }
       // the run reaching lane 63 stays open
-      ckey = lane63(key);
-      cw = lane63(vw);
-      cr = lane63(vr);
-      ci = lane63(vi);
-      cn = lane63(vn);
+      ckey = read_lane<63>(key);
+      cw = read_lane<63>(vw);
+      cr = read_lane<63>(vr);
+      ci = read_lane<63>(vi);
+      cn = read_lane<63>(vn);
     }
     if (ckey != kNoRun && lane == 0) {
       double *c = &acc[base + (int32_t)ckey].x;

@@ -323,16 +323,18 @@ def _morton_changes(u, v, theta):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_boundary_crossing_runs(precision):
+@pytest.mark.parametrize("n_src", [150, 5])
+def test_boundary_crossing_runs(precision, n_src):
     """Visibilities packed densely around cell boundaries, so that along the
     sorted order every source moves back and forth between neighbouring cells
-    many times (open runs swapped, older runs flushed on a third cell): 150
-    sources (three source tiles of the source-parallel kernel), cells and
-    counts bit-exact against the oracle, sums to rounding."""
+    many times: 150 sources (three source tiles of the source-parallel
+    kernel: open runs swapped, older runs flushed on a third cell) and 5
+    sources (the visibility-parallel kernel: short runs inside and across
+    the lanes of a step), cells and counts bit-exact against the oracle,
+    sums to rounding."""
     mixed = precision == "mixed"
     c = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64))
     g = np.random.default_rng(2024)
-    n_src = 150
     alpha = np.exp(g.normal(0.0, 0.3, n_src))
     cat = synth.Catalogue(g.uniform(-2e-3, 2e-3, n_src), g.uniform(-2e-3, 2e-3, n_src),
                           g.uniform(20e-6, 200e-6, n_src), alpha,

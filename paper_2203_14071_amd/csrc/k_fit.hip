@@ -42,6 +42,28 @@ constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
 template <int R, bool kMixed>
 constexpr int knots_per_pass() { return (kMixed && R == 20) ? 10 : R; }
 
+// FP64 sums over cells [cb, ce) of one grid point for KP knots (the first
+// n_use of them): D_k += W Re(Vbar) f, M_k += W f^2 with f = (2/3) f_c.
+template <int KP>
+__device__ __forceinline__ void cell_sums_f64(const double4 *__restrict__ cells, int64_t cb, int64_t ce, double a11,
+                                              double a12, double a22, const double *sk, int n_use, double *D,
+                                              double *M) {
+  for (int64_t c = cb; c < ce; ++c) {
+    const double4 cl = cells[c];
+    const double ku = fma(a11, cl.x, a12 * cl.y);
+    const double kv = fma(a12, cl.x, a22 * cl.y);
+    const double q = fma(ku, ku, kv * kv);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (k < n_use) {
+        const double f = pow_m32_f64(fma(sk[k], q, 1.0));           // (2/3) f_c
+        D[k] = fma(cl.w, f, D[k]);
+        M[k] = fma(cl.z * f, f, M[k]);
+      }
+    }
+  }
+}
+
 // ln L(e) of source s at (e1, e2), |e| < 1; NaN for an empty facet.
 template <int R, bool kExact, bool kMixed>
 __device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int s, double e1, double e2) {
@@ -64,21 +86,7 @@ __device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int
       double sk[KP];
 #pragma unroll
       for (int k = 0; k < KP; ++k) sk[k] = k0 + k < num_r ? a.sk[k0 + k] * g : 0.0;
-      const double4 *__restrict__ cells = a.fit64;
-      for (int64_t c = c0; c < c1; ++c) {
-        const double4 cl = cells[c];
-        const double ku = fma(a11, cl.x, a12 * cl.y);
-        const double kv = fma(a12, cl.x, a22 * cl.y);
-        const double q = fma(ku, ku, kv * kv);
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-          if (k0 + k < num_r) {
-            const double f = pow_m32_f64(fma(sk[k], q, 1.0));       // (2/3) f_c
-            D[k] = fma(cl.w, f, D[k]);
-            M[k] = fma(cl.z * f, f, M[k]);
-          }
-        }
-      }
+      cell_sums_f64<KP>(a.fit64, c0, c1, a11, a12, a22, sk, num_r - k0, D, M);
     } else {
       const float a11 = (float)(1.0 + e1), a12 = (float)e2, a22 = (float)(1.0 - e1);
       float sk[KP];
@@ -304,6 +312,76 @@ __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
   eval_point<R, kExact, kMixed, NP>(a, num_r, s, j);
 }
 
+// Few sources (FP64 form, position fixed, R knots in one pass): the grid of
+// one source is only ~100 waves, each walking all of the source's cells, so
+// the cells are cut into a.parts ranges (blockIdx.z), each thread writes its
+// range's D_k and M_k, and k_fit_join adds the ranges in order and forms
+// ln L(e) as loglike_e does.
+template <int R>
+__global__ __launch_bounds__(256) void k_fit_part(FitArgs a) {
+  const int s = blockIdx.y, part = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_valid) return;
+  if (a.redo && !a.redo[s]) return;
+  const int64_t c0 = a.offsets[s], c1 = a.offsets[s + 1];
+  const int64_t len = (c1 - c0 + a.parts - 1) / a.parts;
+  const int64_t cb = min(c1, c0 + part * len), ce = min(c1, cb + len);
+  const int idx = a.epts[j];
+  const int i1 = idx / a.n_e, i2 = idx - (idx / a.n_e) * a.n_e;
+  const int ctr = (a.n_e - 1) / 2;
+  const double e1 = (double)(i1 - ctr) * a.e_step, e2 = (double)(i2 - ctr) * a.e_step;
+  const double det = 1.0 - e1 * e1 - e2 * e2;
+  const double g = 1.0 / (det * det);
+  double D[R], M[R], sk[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    D[k] = M[k] = 0.0;
+    sk[k] = a.sk[k] * g;
+  }
+  cell_sums_f64<R>(a.fit64, cb, ce, 1.0 + e1, e2, 1.0 - e1, sk, R, D, M);
+  double *out = a.part_sums + ((int64_t)s * a.parts + part) * (2 * R) * a.n_valid + j;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    out[(int64_t)k * a.n_valid] = D[k];
+    out[(int64_t)(R + k) * a.n_valid] = M[k];
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_fit_join(FitArgs a) {
+  const int s = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_valid) return;
+  if (a.redo && !a.redo[s]) return;
+  double *dst = a.lsurf + (int64_t)s * a.n_valid + j;
+  if (a.offsets[s + 1] == a.offsets[s]) {
+    *dst = NAN;
+    return;
+  }
+  double D[R], M[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) D[k] = M[k] = 0.0;
+  for (int part = 0; part < a.parts; ++part) {
+    const double *in = a.part_sums + ((int64_t)s * a.parts + part) * (2 * R) * a.n_valid + j;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      D[k] += in[(int64_t)k * a.n_valid];
+      M[k] += in[(int64_t)(R + k) * a.n_valid];
+    }
+  }
+  const double *lw = a.logw + (int64_t)s * a.num_r;
+  double bm = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    D[k] = lw[k] + (D[k] * D[k] / (2.0 * M[k]) - 0.5 * log(M[k]) - kLnPowM32Scale);
+    bm = fmax(bm, D[k]);
+  }
+  double bs = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) bs += exp(D[k] - bm);
+  *dst = bm + log(bs);
+}
+
 // Windowed launch: blockIdx.y = source, one thread per position of the
 // source's inclusive box (i1lo, i1hi, i2lo, i2hi) in row-major order, then,
 // with a check stride S, per lattice point c + S q (both axes, |q| <= c / S)
@@ -470,6 +548,10 @@ hipError_t launch(const FitArgs &a, hipStream_t st) {
     const int lattice = (a.check_stride > 0 && a.lattice_pass != 2) ? (2 * h + 1) * (2 * h + 1) : 0;
     const int positions = (a.lattice_pass == 1 ? 0 : a.n_e * a.n_e) + lattice;
     RLF_FIT_DISPATCH(k_fit_window, dim3((positions + 255) / 256, a.n_src), a);
+  } else if (!kMixed && a.parts > 1 && a.num_r == 20) {
+    const unsigned bx = (unsigned)((a.n_valid + 255) / 256);
+    hipLaunchKernelGGL(k_fit_part<20>, dim3(bx, a.n_src, a.parts), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_fit_join<20>, dim3(bx, a.n_src), dim3(256), 0, st, a);
   } else {
     RLF_FIT_DISPATCH(k_fit, dim3((a.n_valid + 255) / 256, a.n_src), a);
   }

@@ -443,6 +443,7 @@ int rlf_destroy(rlf_ctx *c) {
   dfree(c->d_chan);
   dfree(c->d_err);
   dfree(c->d_absmax);
+  dfree(c->d_part);
   for (auto &sl : c->slot) {
     dfree(sl.d);
     dfree(sl.d32);
@@ -980,6 +981,27 @@ int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa) {
     fa.n_pos = pa.n_pos;
     fa.pos_g64 = pa.g64;
     fa.pos_g32 = pa.g32;
+  }
+  // few sources: split each source's cells over several waves per grid point
+  // (a source alone is ~100 waves; split until ~2048 waves run), unless the
+  // stream is being captured (the partial-sum buffer may have to grow)
+  if (!f->mixed && f->pos_side <= 1 && c->p.num_r == 20) {
+    const int64_t waves = f->n_src * (int64_t)((c->n_valid + 63) / 64);
+    const int64_t parts = std::min<int64_t>(16, 2048 / std::max<int64_t>(1, waves));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(c, hipStreamIsCapturing(c->stream, &cs));
+    if (parts >= 2 && cs == hipStreamCaptureStatusNone) {
+      const int64_t need = f->n_src * parts * 2 * c->p.num_r * (int64_t)c->n_valid;
+      if (need > c->part_cap) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        dfree(c->d_part);
+        c->part_cap = 0;
+        if (int e = dalloc(c, &c->d_part, need)) return e;
+        c->part_cap = need;
+      }
+      fa.parts = (int32_t)parts;
+      fa.part_sums = c->d_part;
+    }
   }
   return RLF_OK;
 }

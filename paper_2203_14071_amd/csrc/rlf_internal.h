@@ -171,6 +171,11 @@ struct FitArgs {
   // lattice-seeded window: 1 = evaluate only the check_stride lattice (window
   // ignored); 2 = the lattice values are already in lsurf (box only)
   int32_t lattice_pass;
+  // few sources, FP64 form, 20 knots, position fixed, full grid: parts > 1
+  // splits each source's cells into that many ranges whose partial sums
+  // [n_src][parts][2 * num_r][n_valid] go to part_sums before being joined
+  int32_t parts;
+  double *part_sums;
 };
 
 // Cross-correlation data of the position marginalisation (one row of n_pos

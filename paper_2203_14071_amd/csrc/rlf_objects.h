@@ -38,6 +38,9 @@ struct rlf_ctx {
   uint64_t tick = 0;
   uint32_t *d_err = nullptr;
   double *d_absmax = nullptr;
+  // partial likelihood sums of split fits (few sources), grown on demand
+  double *d_part = nullptr;
+  int64_t part_cap = 0;
 };
 
 struct rlf_facets {

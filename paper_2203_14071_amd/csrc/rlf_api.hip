@@ -513,6 +513,62 @@ int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_
 
 namespace rlf {
 
+// Per-source facet geometry: theta = K alpha, the half-size bounding every
+// rint(u theta) of the observation (largest |u|, |v| in metres `mx`), and
+// each source's dense block of (2 half + 1)^2 cells.
+int facet_geometry(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const double mx[2],
+                   std::vector<double> &theta, std::vector<SrcGeom> &geom, int64_t &total) {
+  theta.resize((size_t)cat->n_src);
+  geom.resize((size_t)cat->n_src);
+  total = 0;
+  for (int64_t s = 0; s < cat->n_src; ++s) {
+    const double th = c->p.K * (cat->alpha_arcsec[s] * kArcsec);
+    int64_t half = 0;
+    for (int k = 0; k < obs->n_chan; ++k) {
+      const double sc = obs->freq_hz_host[k] / kC;
+      const double tu = std::nearbyint((mx[0] * sc) * th), tv = std::nearbyint((mx[1] * sc) * th);
+      const double t = tu > tv ? tu : tv;
+      if (!(t <= (double)kMaxFacetHalf))
+        return fail(c, RLF_ERANGE, "facet half-size exceeds 16383 cells (alpha * K too large for the uv extent)");
+      half = (int64_t)t > half ? (int64_t)t : half;
+    }
+    theta[(size_t)s] = th;
+    geom[(size_t)s].base = total;
+    geom[(size_t)s].half = (int32_t)half;
+    geom[(size_t)s].side = (int32_t)(2 * half + 1);
+    total += (2 * half + 1) * (2 * half + 1);
+  }
+  return RLF_OK;
+}
+
+// Scale-marginalisation weights ln(c_k) + ln p_s(alpha_k) (log-normal prior)
+// [n_src * num_r].
+std::vector<double> facet_logw(rlf_ctx *c, const rlf_catalog *cat) {
+  const int R = c->p.num_r;
+  std::vector<double> logw((size_t)cat->n_src * R);
+  for (int64_t s = 0; s < cat->n_src; ++s) {
+    const double mu = cat->prior_mu ? cat->prior_mu[s] : c->p.add + c->p.esp * std::log(cat->flux_jy[s] * 1e6);
+    for (int k = 0; k < R; ++k) {
+      const double a = c->knots[k];
+      const double z = std::log(a) - mu;
+      const double lp = -z * z / (2.0 * c->p.r_std * c->p.r_std) - std::log(a * c->p.r_std * std::sqrt(2.0 * M_PI));
+      logw[(size_t)s * R + k] = std::log(c->ck[k]) + lp;
+    }
+  }
+  return logw;
+}
+
+// Extraction lanes take the sources in order of cell size: cell boundaries
+// (rint(u theta)) of neighbouring lanes then nearly coincide, so their cell
+// changes come at nearly the same visibilities and the branches of a wave
+// diverge less.
+std::vector<int32_t> lane_order(const std::vector<double> &theta) {
+  std::vector<int32_t> order(theta.size());
+  for (size_t s = 0; s < theta.size(); ++s) order[s] = (int32_t)s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return theta[(size_t)x] < theta[(size_t)y]; });
+  return order;
+}
+
 // A facet object for `cat`; with `share`, the uv-sorted layout of `share`
 // (made for the same observation) is borrowed instead of sorted again.
 int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const rlf_facets *share,
@@ -548,41 +604,14 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     f->spec_norm = g / obs->n_chan;
   }
   f->alpha.assign(cat->alpha_arcsec, cat->alpha_arcsec + cat->n_src);
-  f->theta.resize((size_t)cat->n_src);
-  f->geom.resize((size_t)cat->n_src);
   int64_t total = 0;
-  for (int64_t s = 0; s < cat->n_src; ++s) {
-    const double th = c->p.K * (cat->alpha_arcsec[s] * kArcsec);
-    int64_t half = 0;
-    for (int k = 0; k < obs->n_chan; ++k) {
-      const double sc = obs->freq_hz_host[k] / kC;
-      const double tu = std::nearbyint((mx[0] * sc) * th), tv = std::nearbyint((mx[1] * sc) * th);
-      const double t = tu > tv ? tu : tv;
-      if (!(t <= (double)kMaxFacetHalf)) {
-        delete f;
-        return fail(c, RLF_ERANGE, "facet half-size exceeds 16383 cells (alpha * K too large for the uv extent)");
-      }
-      half = (int64_t)t > half ? (int64_t)t : half;
-    }
-    f->theta[(size_t)s] = th;
-    f->geom[(size_t)s].base = total;
-    f->geom[(size_t)s].half = (int32_t)half;
-    f->geom[(size_t)s].side = (int32_t)(2 * half + 1);
-    total += (2 * half + 1) * (2 * half + 1);
+  if (int e = facet_geometry(c, obs, cat, mx, f->theta, f->geom, total)) {
+    delete f;
+    return e;
   }
   f->dense_total = total;
-  // scale-marginalisation weights: ln(c_k) + ln p_s(alpha_k), log-normal prior
-  const int R = c->p.num_r;
-  std::vector<double> logw((size_t)cat->n_src * R);
-  for (int64_t s = 0; s < cat->n_src; ++s) {
-    const double mu = cat->prior_mu ? cat->prior_mu[s] : c->p.add + c->p.esp * std::log(cat->flux_jy[s] * 1e6);
-    for (int k = 0; k < R; ++k) {
-      const double a = c->knots[k];
-      const double z = std::log(a) - mu;
-      const double lp = -z * z / (2.0 * c->p.r_std * c->p.r_std) - std::log(a * c->p.r_std * std::sqrt(2.0 * M_PI));
-      logw[(size_t)s * R + k] = std::log(c->ck[k]) + lp;
-    }
-  }
+  f->dense_cap = total;
+  const std::vector<double> logw = facet_logw(c, cat);
   int rc = RLF_OK;
   do {
     if ((rc = dalloc(c, &f->d_src, f->n_src))) break;
@@ -603,7 +632,7 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     } else {
       if ((rc = dalloc(c, &f->cells.fit64, total))) break;
     }
-    if ((rc = dalloc(c, &f->d_logw, f->n_src * R))) break;
+    if ((rc = dalloc(c, &f->d_logw, f->n_src * c->p.num_r))) break;
     if ((rc = dalloc(c, &f->d_lsurf, f->n_src * (int64_t)c->n_valid))) break;
     if ((rc = dalloc(c, &f->d_redo, f->n_src))) break;
     if ((rc = dalloc(c, &f->d_win, f->n_src * 4))) break;
@@ -615,13 +644,7 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
   }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpy(f->d_geom, f->geom.data(), sizeof(SrcGeom) * f->geom.size(), hipMemcpyHostToDevice);
-  // extraction lanes take the sources in order of cell size: cell boundaries
-  // (rint(u theta)) of neighbouring lanes then nearly coincide, so their runs
-  // end at nearly the same visibilities and the flushes of a wave cluster
-  std::vector<int32_t> order((size_t)f->n_src);
-  for (int64_t s = 0; s < f->n_src; ++s) order[(size_t)s] = (int32_t)s;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return f->theta[(size_t)x] < f->theta[(size_t)y]; });
+  const std::vector<int32_t> order = lane_order(f->theta);
   if (e == hipSuccess) e = hipMemcpy(f->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(f->acc.cell, 0, sizeof(double4) * (size_t)total);
@@ -653,6 +676,73 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     return r;
   }
   *out = f;
+  return RLF_OK;
+}
+
+// Point an existing facet object at another catalogue of as many sources
+// (same observation): new geometry, weights, lane order and model table;
+// the dense arrays are reused while they are large enough, the uv-sorted
+// layout (owned or borrowed) is kept, and positions go back to fixed.
+int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets *f) {
+  if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
+  if (int e = check_obs(c, obs)) return e;
+  if (int e = check_cat(c, cat, true)) return e;
+  if (cat->n_src != f->n_src) return fail(c, RLF_EINVAL, "retarget: source count differs");
+  if (int e = set_device(c)) return e;
+  std::vector<double> theta;
+  std::vector<SrcGeom> geom;
+  int64_t total = 0;
+  if (int e = facet_geometry(c, obs, cat, f->mx, theta, geom, total)) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));          // queued kernels may still read the tables
+  if (total > f->dense_cap) {
+    dfree(f->acc.cell);
+    dfree(f->cells.ix);
+    dfree(f->cells.iy);
+    dfree(f->cells.count);
+    dfree(f->cells.wsum);
+    dfree(f->cells.vre);
+    dfree(f->cells.vim);
+    dfree(f->cells.fit64);
+    dfree(f->cells.fit32);
+    if (f->d_pos_g) (void)hipFree(f->d_pos_g);
+    f->d_pos_g = nullptr;
+    f->pos_cap = 0;
+    f->dense_cap = 0;
+    f->dense_total = 0;
+    int rc = RLF_OK;
+    do {
+      if ((rc = dalloc(c, &f->acc.cell, total))) break;
+      if ((rc = dalloc(c, &f->cells.ix, total))) break;
+      if ((rc = dalloc(c, &f->cells.iy, total))) break;
+      if ((rc = dalloc(c, &f->cells.count, total))) break;
+      if ((rc = dalloc(c, &f->cells.wsum, total))) break;
+      if ((rc = dalloc(c, &f->cells.vre, total))) break;
+      if ((rc = dalloc(c, &f->cells.vim, total))) break;
+      if (f->mixed) {
+        if ((rc = dalloc(c, &f->cells.fit32, total))) break;
+      } else {
+        if ((rc = dalloc(c, &f->cells.fit64, total))) break;
+      }
+    } while (0);
+    if (rc != RLF_OK) return rc;                       // the object stays unusable until freed
+    f->dense_cap = total;
+  }
+  const std::vector<double> logw = facet_logw(c, cat);
+  const std::vector<int32_t> order = lane_order(theta);
+  HIPCHK(c, hipMemcpy(f->d_geom, geom.data(), sizeof(SrcGeom) * geom.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(f->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(f->acc.cell, 0, sizeof(double4) * (size_t)total));
+  HIPCHK(c, hipMemset(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1)));
+  HIPCHK(c, hipMemset(f->d_redo, 0, sizeof(int32_t) * (size_t)f->n_src));
+  if (int e = upload_sources(c, cat, f->d_src, f->d_src32)) return e;
+  f->model_key = cat_key(cat);
+  f->alpha.assign(cat->alpha_arcsec, cat->alpha_arcsec + cat->n_src);
+  f->theta.swap(theta);
+  f->geom.swap(geom);
+  f->dense_total = total;
+  f->pos_side = 1;
+  f->pos_step = 0.0;
   return RLF_OK;
 }
 

@@ -47,6 +47,7 @@ struct rlf_facets {
   rlf_ctx *ctx = nullptr;
   int64_t n_src = 0;
   int64_t dense_total = 0;
+  int64_t dense_cap = 0;                     // dense cells the accumulator and cell arrays hold
   int mixed = 0;
   double spec_norm = 1.0;                    // mean spectral factor over the channels
   double mx[2] = {0.0, 0.0};                 // largest |u_m|, |v_m| of the observation
@@ -119,6 +120,11 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
 // Likelihood arguments of a facet object (position marginalisation
 // included); enqueues the cross-correlation data when offsets are set.
 int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa);
+
+// The same facet object for another catalogue of as many sources (same
+// observation); the uv-sorted layout is kept, the dense arrays reused while
+// large enough.
+int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_facets *f);
 
 // Extraction into f: with `vis`, first the gather into f's sorted layout
 // (subtract = 1: minus f's own catalogue models); with vis NULL the sorted

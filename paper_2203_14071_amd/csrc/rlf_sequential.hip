@@ -125,8 +125,14 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
     const SubCat sub = subset(cat, idx, e1, e2);
     const rlf_catalog v = sub.view();
     rlf_facets *f = nullptr;
-    if (int e = create_facets(c, obs, &v, master, &f)) return e;
-    sc.facets.push_back(f);
+    if (master && v.n_src == master->n_src) {
+      // a chunk of the first chunk's size reuses its facet object
+      if (int e = retarget_facets(c, obs, &v, master)) return e;
+      f = master;
+    } else {
+      if (int e = create_facets(c, obs, &v, master, &f)) return e;
+      sc.facets.push_back(f);
+    }
     if (!master) {
       // residual of the starting model, kept in place from here on
       master = f;

@@ -314,11 +314,13 @@ int rlf_refine_sources(rlf_ctx *ctx, rlf_facets *facets, int32_t np_max, double 
  *   out      device [n_src] final estimate of every source (flags required,
  *            surface ignored)
  *   e1_host, e2_host   host [n_src] final sky-model shapes
- * The residual is kept in a library-allocated device buffer the size of
- * obs->vis and updated in place (R += old models, R -= new models of the
- * refined sources); obs->vis is not modified.  Synchronises after every
- * chunk (the host decides which shapes enter the model).  RLF_EINVAL for
- * chunk < 1 or a NULL argument. */
+ * The residual is kept in the uv-sorted layout of the first chunk's facet
+ * object (FP64 form: plus a library-allocated unweighted copy, 16 bytes per
+ * visibility) and updated in place (R += old models, R -= new models of the
+ * refined sources, with the arithmetic of rlf_model_vis); obs->vis is not
+ * modified.  Chunks of the first chunk's size reuse its facet object.
+ * Synchronises after every chunk (the host decides which shapes enter the
+ * model).  RLF_EINVAL for chunk < 1 or a NULL argument. */
 int rlf_fit_sequential(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat, int64_t chunk, int32_t refit_bad,
                        const rlf_fit_out *out, double *e1_host, double *e2_host);
 

@@ -17,8 +17,8 @@ pytestmark = pytest.mark.gpu
 BAD_SIGMA = 0.14          # flags about half of this field's fits, so the refit runs
 
 
-def _field():
-    cfg = dataclasses.replace(synth.small_config(0, n_ant=12, n_time=20, n_src=8), field_deg=0.05)
+def _field(n_src=8):
+    cfg = dataclasses.replace(synth.small_config(0, n_ant=12, n_time=20, n_src=n_src), field_deg=0.05)
     o = synth.observation(0, cfg)
     cat = synth.catalogue(cfg, np.random.default_rng(21))
     rng = np.random.default_rng(22)
@@ -27,9 +27,13 @@ def _field():
     return o, cat, vis
 
 
-@pytest.mark.parametrize("precision,chunk", [("fp64", 1), ("fp64", 3), ("fp64", 8), ("mixed", 3)])
-def test_sequential_matches_oracle(precision, chunk):
-    o, cat, vis = _field()
+@pytest.mark.parametrize("precision,chunk,n_src", [("fp64", 1, 8), ("fp64", 3, 8), ("fp64", 8, 8), ("mixed", 3, 8),
+                                                 ("fp64", 9, 20), ("mixed", 9, 20)])
+def test_sequential_matches_oracle(precision, chunk, n_src):
+    """Chunks of 9 of 20 sources: the source-parallel extraction kernel for
+    the 9-source chunks (the second reusing the first chunk's facet object)
+    and the small-catalogue kernel for the last 2."""
+    o, cat, vis = _field(n_src)
     mixed = precision == "mixed"
     n = cat.n_src
     start = SkyCatalogue(cat.l, cat.m, cat.flux_jy, cat.alpha_arcsec, np.zeros(n), np.zeros(n))

@@ -59,11 +59,11 @@ TRAFFIC_BYTES = {"fp64": {"extract": 2788.7e6, "fit": 356.6e6, "model": 521.2e6}
 # Slots per unit of work are the VALU instructions of the compiled hot loop
 # at their measured gfx950 cost (FP64 and FP32 add/mul/FMA/round and FP32
 # v_sin/v_cos/v_rsq 1, v_rsq FP64 4):
-#   extraction FP64 42 = phase 3, reduction 3, sincos polynomials + table
-#     index + rotation 12, profile (quadratic form 3, rsq 4, correction 4,
-#     flux 1) 12, cell index 4, run key + compare 2, run sums 6;
-#     mixed 30 (phase and fractional part in FP64, v_sin/v_cos, FP32
-#     rotation and profile, widening, FP64 run sums)
+#   extraction FP64 41 = phase 3, reduction 3, sincos polynomials + table
+#     index + rotation 12, profile (quadratic form 3 with the flux folded
+#     into it, rsq 4, correction 4) 11, cell index 4, run key + compare 2,
+#     run sums 6;  mixed 29 (phase and fractional part in FP64, v_sin/v_cos,
+#     FP32 rotation and profile, widening, FP64 run sums)
 #   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
 #     D 1, Mm 2;  mixed 7 = x 1, rsq 1, cube 2, D 1, Mm 2; plus 5 per
 #     (cell, point) shared by the knots (mixed 10: two knot passes)
@@ -72,8 +72,8 @@ TRAFFIC_BYTES = {"fp64": {"extract": 2788.7e6, "fit": 356.6e6, "model": 521.2e6}
 #     conversion 2, sin + cos 2, profile 3 + rsq 1 + cube 2, amplitude 1,
 #     accumulate 2
 SLOT_PEAK = 256 * 64 * 2.4e9
-SLOTS = {"fp64": {"extract": 42, "fit_knot": 12, "fit_point": 5, "model": 32},
-         "mixed": {"extract": 30, "fit_knot": 7, "fit_point": 10, "model": 16}}
+SLOTS = {"fp64": {"extract": 41, "fit_knot": 12, "fit_point": 5, "model": 32},
+         "mixed": {"extract": 29, "fit_knot": 7, "fit_point": 10, "model": 16}}
 
 
 def log(*a):

@@ -116,7 +116,7 @@ typedef struct {
 typedef struct {
   int64_t n_src;                 /* > 0                                                */
   const double *l, *m;           /* direction cosines, l^2 + m^2 < 1                   */
-  const double *flux_jy;         /* integrated flux at ref_freq_hz, finite             */
+  const double *flux_jy;         /* integrated flux at ref_freq_hz, finite, >= 0        */
   const double *alpha_arcsec;    /* scale length, finite, > 0 (rlf_alpha_from_flux when unknown) */
   const double *e1, *e2;         /* sky-model shape, |e| < 1 (0 = circular start, Sec. 2.2) */
   const double *prior_mu;        /* optional [n_src] ln(alpha_median/arcsec) of the scale prior;

@@ -170,12 +170,20 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
   const uint64_t *__restrict__ wt = swt + j0;                    // weight bits: 0 = skip
 
   if (!kMixed) {
+    // the flux folded into the profile argument: with x' = c0 x and
+    // c0 = (3/2 S)^{-2/3}, pow_m32_f64(x') = (2/3) x'^{-3/2} = S x^{-3/2},
+    // the own model per unit spectral factor, with no multiplication by S
+    // per pair (S = 0: c0 = 1e250, x' >= 1e250 and the term underflows to
+    // exactly zero; c0 finite, so no infinity meets a zero coefficient)
     SrcModel p[NS];
-    double sflux[NS];
+    double c0[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       p[i] = a.src[src[i]];
-      sflux[i] = kPowM32Scale * p[i].flux;
+      c0[i] = p[i].flux > 0.0 ? pow(kPowM32Scale * p[i].flux, -2.0 / 3.0) : 1e250;
+      p[i].q11 *= c0[i];
+      p[i].q12x2 *= c0[i];
+      p[i].q22 *= c0[i];
     }
     const double4 *__restrict__ quad = reinterpret_cast<const double4 *>(squad) + j0;
     const double2 *__restrict__ res = reinterpret_cast<const double2 *>(sres) + j0;
@@ -205,8 +213,8 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
         for (int i = 0; i < NS; ++i) {
           const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
           const double2 cs = cis2pi_f64(ph, tab);
-          const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, 1.0)));
-          const double own = sflux[i] * pow_m32_f64(x);             // own model / spec, real after the shift
+          const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, c0[i])));
+          const double own = pow_m32_f64(x);                        // own model / spec, real after the shift
           enter_cell(L[i], acc, a.err, nproc, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)));
           // w z = (w R) exp(-2 pi i ph) + (w spec) own
           L[i].rw += ww;
@@ -217,9 +225,20 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
       }
     }
   } else {
+    // the flux folded into the profile argument as in the FP64 form:
+    // c0 = S^{-2/3}, rsq(c0 x)^3 = S x^{-3/2} (S = 0: c0 = 1e36, x' either
+    // overflows, rsq = 0, or its rsqrt cube underflows to zero)
     SrcMixed p[NS];
+    float c0[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) p[i] = a.src32[src[i]];
+    for (int i = 0; i < NS; ++i) {
+      p[i] = a.src32[src[i]];
+      const double c = p[i].flux > 0.0f ? pow((double)p[i].flux, -2.0 / 3.0) : 1e36;
+      c0[i] = (float)c;
+      p[i].q11 = (float)(c * p[i].q11);
+      p[i].q12x2 = (float)(c * p[i].q12x2);
+      p[i].q22 = (float)(c * p[i].q22);
+    }
     const float4 *__restrict__ quad = reinterpret_cast<const float4 *>(squad) + j0;
     const float2 *__restrict__ res = reinterpret_cast<const float2 *>(sres) + j0;
     for (int jl = 0; jl < len; jl += G) {
@@ -252,9 +271,9 @@ __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, 
           const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
           float zr = fmaf(rg[t].x, cs, rg[t].y * sn);
           const float zi = fmaf(rg[t].y, cs, -(rg[t].x * sn));
-          const float x = fmaf(p[i].q11, qg[t].x, fmaf(p[i].q12x2, qg[t].y, fmaf(p[i].q22, qg[t].z, 1.0f)));
+          const float x = fmaf(p[i].q11, qg[t].x, fmaf(p[i].q12x2, qg[t].y, fmaf(p[i].q22, qg[t].z, c0[i])));
           const float q = __builtin_amdgcn_rsqf(x);
-          zr = fmaf(qg[t].w * p[i].flux, q * q * q, zr);
+          zr = fmaf(qg[t].w, q * q * q, zr);
           enter_cell(L[i], acc, a.err, nproc, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)));
           L[i].rw += ww;
           L[i].rzr = fma(ww, (double)zr, L[i].rzr);

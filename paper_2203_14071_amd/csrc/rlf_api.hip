@@ -123,7 +123,8 @@ int check_cat(rlf_ctx *c, const rlf_catalog *k, bool need_prior_flux) {
   for (int64_t s = 0; s < k->n_src; ++s) {
     const double l = k->l[s], m = k->m[s], e1 = k->e1[s], e2 = k->e2[s];
     if (!is_fin(l) || !is_fin(m) || !(l * l + m * m < 1.0)) return fail(c, RLF_EINVAL, "catalog: need l^2+m^2 < 1");
-    if (!is_fin(k->flux_jy[s])) return fail(c, RLF_EINVAL, "catalog: flux must be finite");
+    if (!is_fin(k->flux_jy[s]) || !(k->flux_jy[s] >= 0.0))
+      return fail(c, RLF_EINVAL, "catalog: flux must be finite and >= 0");
     if (need_prior_flux && !k->prior_mu && !(k->flux_jy[s] > 0))
       return fail(c, RLF_EINVAL, "catalog: flux must be > 0 for the Eq. 4 prior (or give prior_mu)");
     if (!(k->alpha_arcsec[s] > 0) || !is_fin(k->alpha_arcsec[s])) return fail(c, RLF_EINVAL, "catalog: alpha must be finite and > 0");

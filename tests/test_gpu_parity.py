@@ -375,3 +375,48 @@ def test_boundary_crossing_runs(precision, n_src):
         assert np.max(np.abs(fac["vbar"][a:b] - ref.vbar)) <= 2e-5 * (scale + cat.flux_jy[s]), s
     f.free()
     c.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_flux_sources(precision):
+    """Sources of zero flux (some circular) in a catalogue of 12 (the
+    source-parallel kernel): their own model is zero, so their facets are the
+    shifted residual alone, against the oracle; a negative flux is rejected."""
+    mixed = precision == "mixed"
+    c = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64))
+    cfg = synth.small_config(0, n_ant=16, n_time=30, n_src=12)
+    o = synth.observation(0, cfg)
+    cat = synth.catalogue(cfg, np.random.default_rng(41))
+    flux = cat.flux_jy.copy()
+    flux[[1, 4, 7, 10]] = 0.0
+    e1, e2 = cat.e1.copy(), cat.e2.copy()
+    e1[[4, 10]] = 0.0
+    e2[[4, 10]] = 0.0
+    cat = synth.Catalogue(cat.l, cat.m, flux, cat.alpha_arcsec, e1, e2)
+    rng = np.random.default_rng(42)
+    n = o.n_rows * o.n_chan
+    resid = cfg.noise_sigma_jy * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    if mixed:
+        resid = resid.astype(np.complex64).astype(np.complex128)
+        o.weight = o.weight.astype(np.float32).astype(np.float64)
+    obs = G.make_obs(o, resid, mixed=mixed)
+    mu = np.full(cat.n_src, 0.1)                                    # the Eq. 4 prior needs a positive flux
+    f = c.facets_create(obs, cat, prior_mu=mu)
+    c.extract_facets(obs, cat, obs.vis, f, prior_mu=mu)
+    fac = f.copy()
+    scale = float(np.max(np.abs(resid)))
+    for s in range(cat.n_src):
+        ref = G.oracle_facet(o, resid, cat, s)
+        a, b = int(fac["offsets"][s]), int(fac["offsets"][s + 1])
+        assert b - a == ref.n_cells, s
+        for key in ("ix", "iy", "count"):
+            assert np.array_equal(fac[key][a:b], getattr(ref, key)), (s, key)
+        tol = (2e-5 if mixed else G.VBAR_TOL) * (scale + cat.flux_jy[s])
+        assert np.all(np.isfinite(fac["vbar"][a:b])), s
+        assert np.max(np.abs(fac["vbar"][a:b] - ref.vbar)) <= tol, s
+    f.free()
+    bad = synth.Catalogue(cat.l, cat.m, np.where(np.arange(cat.n_src) == 3, -1e-5, flux), cat.alpha_arcsec, e1, e2)
+    with pytest.raises(rlf.RlfError) as e:
+        c.facets_create(obs, bad, prior_mu=mu)
+    assert e.value.code == rlf.RLF_EINVAL
+    c.close()

@@ -49,11 +49,11 @@ MODEL_FLOP_PAIR = 19
 # bracket) at this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (each
 # scaled by a plain copy's reading), for the kernels as they are now; None
 # where not measured.  profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md:
-#   extraction (k_extract): fetch 1692.3 / 1195.6 MB, write 1096.4 / 964.9 MB
+#   extraction (k_extract): fetch 1720.8 / 1195.6 MB, write 1096.4 / 964.9 MB
 #   likelihood (k_fit + k_estimate): fetch 154.8 + 150.2 / 78.9 + 150.0 MB,
 #     write 51.3 + 0.3 / 51.3 + 0.3 MB
 #   sky model (k_model): fetch 372.9 / 298.4 MB, write 148.3 / 74.1 MB
-TRAFFIC_BYTES = {"fp64": {"extract": 2788.7e6, "fit": 356.6e6, "model": 521.2e6},
+TRAFFIC_BYTES = {"fp64": {"extract": 2817.2e6, "fit": 356.6e6, "model": 521.2e6},
                  "mixed": {"extract": 2160.5e6, "fit": 280.5e6, "model": 372.5e6}}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Slots per unit of work are the VALU instructions of the compiled hot loop
@@ -62,7 +62,7 @@ TRAFFIC_BYTES = {"fp64": {"extract": 2788.7e6, "fit": 356.6e6, "model": 521.2e6}
 #   extraction FP64 41 = phase 3, reduction 3, sincos polynomials + table
 #     index + rotation 12, profile (quadratic form 3 with the flux folded
 #     into it, rsq 4, correction 4) 11, cell index 4, run key + compare 2,
-#     run sums 6;  mixed 29 (phase and fractional part in FP64, v_sin/v_cos,
+#     run sums 6;  mixed 30 (phase and fractional part in FP64, v_sin/v_cos,
 #     FP32 rotation and profile, widening, FP64 run sums)
 #   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
 #     D 1, Mm 2;  mixed 7 = x 1, rsq 1, cube 2, D 1, Mm 2; plus 5 per
@@ -73,7 +73,7 @@ TRAFFIC_BYTES = {"fp64": {"extract": 2788.7e6, "fit": 356.6e6, "model": 521.2e6}
 #     accumulate 2
 SLOT_PEAK = 256 * 64 * 2.4e9
 SLOTS = {"fp64": {"extract": 41, "fit_knot": 12, "fit_point": 5, "model": 32},
-         "mixed": {"extract": 29, "fit_knot": 7, "fit_point": 10, "model": 16}}
+         "mixed": {"extract": 30, "fit_knot": 7, "fit_point": 10, "model": 16}}
 
 
 def log(*a):

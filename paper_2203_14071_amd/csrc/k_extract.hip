@@ -125,9 +125,10 @@ __device__ __forceinline__ void enter_cell(LaneSrc &L, double4 *__restrict__ acc
 // |u|, |v| with the same rounding chain, so every index is inside its facet;
 // the bound is still checked whenever a new cell's run starts (err bit 0).
 //
-// Occupancy: the FP64 form is held to 64 VGPRs (eight waves per SIMD; only a
-// value live across the whole loop spills, outside it), the mixed form fits
-// eight waves by itself.
+// Occupancy: the FP64 form is held to 64 VGPRs (eight waves per SIMD; the
+// few values that spill, the lane's dense-block base among them, are
+// reloaded only on the rare third-cell flush and after the loop), the mixed
+// form fits eight waves by itself.
 template <bool kMixed, int NS, int G>
 __global__ __launch_bounds__(256, kMixed ? 6 : 8) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
                                                  const void *__restrict__ squad, const void *__restrict__ sres,

@@ -151,7 +151,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": x.numel() * 4, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -577,7 +577,7 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
         position.append({"position_sigma_arcsec": sig, "fits": rows})
         fp.free()
 
-    # the lattice-seeded window fit (mode 2) on the same facets, judged by the
+    # the lattice-seeded window fit (mode 2) on the same facets, compared with the
     # full-grid fit of the timed steps
     lattice = []
     lout = {k: torch.empty_like(v) for k, v in out.items()}

@@ -52,7 +52,7 @@ typedef enum {
   RLF_ENOMEM = -2,        /* device or host allocation failed                          */
   RLF_EDEVICE = -3,       /* a HIP runtime call failed; rlf_last_error() has its text  */
   RLF_ERANGE = -4,        /* a facet or the visibility count exceeds supported sizes  */
-  RLF_EUNSUPPORTED = -5   /* valid request this build does not implement               */
+  RLF_EUNSUPPORTED = -5   /* valid request the library does not implement              */
 } rlf_status;
 
 typedef enum { RLF_FP64 = 0, RLF_MIXED = 1 } rlf_precision;
@@ -356,7 +356,7 @@ int rlf_pass_free(rlf_pass *pass);
 /* ---- Grid-narrowing network (not in the paper) --------------------------
  * An MLP maps a facet to (e1, e2, ln alpha) and their log-variances; its
  * predictions centre narrowed ellipticity windows for rlf_fit_sources
- * (mode 1 with fallback), the full-grid fit staying the judge.
+ * (mode 1 with fallback), the full-grid fit staying the reference.
  *   input   8192 values: the facet's cells with -32 <= ix, iy <= 31,
  *           Vbar / (S g) (S the catalogue flux at nu_ref, g the observation's
  *           mean spectral factor of Eq. 1) clipped to [-4, 4], Re at (iy+32)*64 + ix+32, Im at

@@ -1,7 +1,7 @@
 """The learned grid narrowing end to end: simulate training facets with the
 method, train the network on the GPU with the library's kernels, then on the
 10,000-source config-3 field compare the narrowed fit (windows from the
-network, full-grid fallback) with the plain full-grid fit, the judge of its
+network, full-grid fallback) with the plain full-grid fit, the reference for its
 error: RMS(e_window - e_full) <= 1e-3 while evaluating a fraction of the grid.
 A source is refitted on the full grid when a member of its window's 5 % set
 sits on an inner window edge, its window holds no valid grid point, or a

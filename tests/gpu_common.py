@@ -11,7 +11,7 @@ import numpy as np
 import oracle
 from paper_2203_14071_amd import rlf, synth
 
-# Tolerances (derivation in DESIGN.md, "Parity tolerances"):
+# Tolerances and where they come from:
 #  * visibilities: the oracle forms 2*pi*phi before its sin/cos, an absolute
 #    phase rounding of |2 pi phi| * 2^-53 (<= 1e-12 rad at 1,500 turns); the
 #    kernels reduce phi exactly.  Per source term the difference is at most

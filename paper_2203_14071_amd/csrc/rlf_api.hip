@@ -175,6 +175,45 @@ SrcMixed to_mixed(const SrcModel &m) {
   return r;
 }
 
+constexpr size_t kPinnedRing = (size_t)8 << 20;   // bytes of the upload staging ring
+
+}  // namespace
+
+namespace rlf {
+
+int upload_async(rlf_ctx *c, void *dst, const void *src, size_t bytes) {
+  if (bytes == 0) return RLF_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(c, hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(c, RLF_EINVAL, "table upload while the stream is being captured");
+  if (bytes > kPinnedRing / 4) {                      // large tables: a plain copy once the stream is idle
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return RLF_OK;
+  }
+  if (!c->pinned) {
+    void *p = nullptr;
+    HIPCHK(c, hipHostMalloc(&p, kPinnedRing, hipHostMallocDefault));
+    c->pinned = static_cast<char *>(p);
+    c->pinned_off = 0;
+  }
+  size_t off = (c->pinned_off + 255) & ~(size_t)255;
+  if (off + bytes > kPinnedRing) {                    // wrap: every earlier copy must have run
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    off = 0;
+  }
+  std::memcpy(c->pinned + off, src, bytes);
+  HIPCHK(c, hipMemcpyAsync(dst, c->pinned + off, bytes, hipMemcpyHostToDevice, c->stream));
+  c->pinned_off = off + bytes;
+  return RLF_OK;
+}
+
+}  // namespace rlf
+
+namespace {
+
+// Source tables of a catalogue, uploaded behind the work already queued on
+// the stream (kernels still reading the old tables run first).
 int upload_sources(rlf_ctx *c, const rlf_catalog *k, SrcModel *dst, SrcMixed *dst32) {
   std::vector<SrcModel> h((size_t)k->n_src);
   std::vector<SrcMixed> h32((size_t)k->n_src);
@@ -182,10 +221,8 @@ int upload_sources(rlf_ctx *c, const rlf_catalog *k, SrcModel *dst, SrcMixed *ds
     h[(size_t)s] = pack_source(c->p, k, s);
     h32[(size_t)s] = to_mixed(h[(size_t)s]);
   }
-  HIPCHK(c, hipStreamSynchronize(c->stream));      // no pending kernel may still read the tables
-  HIPCHK(c, hipMemcpy(dst, h.data(), sizeof(SrcModel) * h.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(dst32, h32.data(), sizeof(SrcMixed) * h32.size(), hipMemcpyHostToDevice));
-  return RLF_OK;
+  if (int e = upload_async(c, dst, h.data(), sizeof(SrcModel) * h.size())) return e;
+  return upload_async(c, dst32, h32.data(), sizeof(SrcMixed) * h32.size());
 }
 
 // Device source table for rlf_model_vis, reused while the catalogue content is unchanged.
@@ -445,6 +482,8 @@ int rlf_destroy(rlf_ctx *c) {
   dfree(c->d_err);
   dfree(c->d_absmax);
   dfree(c->d_part);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
   for (auto &sl : c->slot) {
     dfree(sl.d);
     dfree(sl.d32);
@@ -455,6 +494,9 @@ int rlf_destroy(rlf_ctx *c) {
 
 int rlf_set_stream(rlf_ctx *c, void *hip_stream) {
   if (!c) return RLF_EINVAL;
+  if (int e = set_device(c)) return e;
+  // uploads staged for the old stream must have run before the ring is reused
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->stream = (hipStream_t)hip_stream;
   return RLF_OK;
 }
@@ -694,8 +736,8 @@ int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
   std::vector<SrcGeom> geom;
   int64_t total = 0;
   if (int e = facet_geometry(c, obs, cat, f->mx, theta, geom, total)) return e;
-  HIPCHK(c, hipStreamSynchronize(c->stream));          // queued kernels may still read the tables
   if (total > f->dense_cap) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));        // queued kernels may still use the arrays
     dfree(f->acc.cell);
     dfree(f->cells.ix);
     dfree(f->cells.iy);
@@ -730,12 +772,13 @@ int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
   }
   const std::vector<double> logw = facet_logw(c, cat);
   const std::vector<int32_t> order = lane_order(theta);
-  HIPCHK(c, hipMemcpy(f->d_geom, geom.data(), sizeof(SrcGeom) * geom.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(f->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(f->d_logw, logw.data(), sizeof(double) * logw.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemset(f->acc.cell, 0, sizeof(double4) * (size_t)total));
-  HIPCHK(c, hipMemset(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1)));
-  HIPCHK(c, hipMemset(f->d_redo, 0, sizeof(int32_t) * (size_t)f->n_src));
+  // everything below is queued behind the work already on the stream
+  if (int e = upload_async(c, f->d_geom, geom.data(), sizeof(SrcGeom) * geom.size())) return e;
+  if (int e = upload_async(c, f->d_order, order.data(), sizeof(int32_t) * order.size())) return e;
+  if (int e = upload_async(c, f->d_logw, logw.data(), sizeof(double) * logw.size())) return e;
+  HIPCHK(c, hipMemsetAsync(f->acc.cell, 0, sizeof(double4) * (size_t)total, c->stream));
+  HIPCHK(c, hipMemsetAsync(f->cells.offsets, 0, sizeof(int64_t) * (size_t)(f->n_src + 1), c->stream));
+  HIPCHK(c, hipMemsetAsync(f->d_redo, 0, sizeof(int32_t) * (size_t)f->n_src, c->stream));
   if (int e = upload_sources(c, cat, f->d_src, f->d_src32)) return e;
   f->model_key = cat_key(cat);
   f->alpha.assign(cat->alpha_arcsec, cat->alpha_arcsec + cat->n_src);

@@ -41,6 +41,9 @@ struct rlf_ctx {
   // partial likelihood sums of split fits (few sources), grown on demand
   double *d_part = nullptr;
   int64_t part_cap = 0;
+  // pinned staging ring of the asynchronous table uploads
+  char *pinned = nullptr;
+  size_t pinned_off = 0;
 };
 
 struct rlf_facets {
@@ -120,6 +123,12 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
 // Likelihood arguments of a facet object (position marginalisation
 // included); enqueues the cross-correlation data when offsets are set.
 int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa);
+
+// Host-to-device copy of a small table on the context's stream without
+// waiting for it: the bytes are staged in a pinned ring, whose space is
+// reused only after a synchronisation of the stream (every copy issued from
+// it has then run).  Refused while the stream is being captured.
+int upload_async(rlf_ctx *c, void *dst, const void *src, size_t bytes);
 
 // The same facet object for another catalogue of as many sources (same
 // observation); the uv-sorted layout is kept, the dense arrays reused while

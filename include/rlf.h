@@ -139,7 +139,9 @@ int rlf_create(rlf_ctx **ctx, int device, void *hip_stream, const rlf_params *p)
  * it must be freed first. */
 int rlf_destroy(rlf_ctx *ctx);
 
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on; synchronises the previous one
+ * first (the library's small table uploads are staged in host memory that
+ * is reused once the stream they were queued on has drained). */
 int rlf_set_stream(rlf_ctx *ctx, void *hip_stream);
 
 /* Wait for all work enqueued by this context. */

@@ -29,6 +29,7 @@
 
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
+#include "rlf_sky.h"
 
 namespace rlf {
 
@@ -352,10 +353,15 @@ __device__ __forceinline__ double read_lane(double x) {
   return __hiloint2double(hi, lo);
 }
 
-template <bool kMixed>
+// kUpd: the residual kept in sorted order is first updated for changed
+// source models (UpdateArgs, as k_update_sorted does, with the same sums),
+// in the same pass: each lane updates its visibilities while the first
+// source is extracted and the extraction reads the updated values.
+template <bool kMixed, bool kUpd>
 __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4 *__restrict__ sgeo,
-                                                    const void *__restrict__ squad, const void *__restrict__ sres,
-                                                    const uint64_t *__restrict__ swt, double4 *__restrict__ acc) {
+                                                    const void *__restrict__ squad, const void *sres,
+                                                    const uint64_t *__restrict__ swt, double4 *__restrict__ acc,
+                                                    UpdateArgs u) {
   __shared__ double2 tab[kMixed ? 1 : kCisTable];
   if (!kMixed) {
     cis_table_init(tab);
@@ -382,7 +388,23 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
       double xf, yf;
       if (!kMixed) {
         const double4 qg = reinterpret_cast<const double4 *>(squad)[j];
-        const double2 rg = reinterpret_cast<const double2 *>(sres)[j];
+        double2 rg;
+        if (kUpd && s == 0) {                                    // uniform
+          rg = make_double2(0.0, 0.0);
+          if (j < a.sv.n_vis) {
+            const double2 ao = sum_f64(gg.x, gg.y, gg.z, u.old64, 0, u.n_old, tab);
+            const double2 an = sum_f64(gg.x, gg.y, gg.z, u.new64, 0, u.n_new, tab);
+            double2 r = u.rs[j];
+            r = make_double2(fma(gg.w, ao.x, r.x), fma(gg.w, ao.y, r.y));
+            r = make_double2(fma(-gg.w, an.x, r.x), fma(-gg.w, an.y, r.y));
+            u.rs[j] = r;
+            const double wpos = __longlong_as_double((long long)wb);
+            rg = make_double2(wpos * r.x, wpos * r.y);
+            reinterpret_cast<double2 *>(u.sv.res)[j] = rg;
+          }
+        } else {
+          rg = reinterpret_cast<const double2 *>(sres)[j];
+        }
         const SrcModel p = a.src[s];
         const double ph = fma(gg.x, p.l, fma(gg.y, p.m, gg.z * p.n1));
         const double2 cs = cis2pi_f64(ph, tab);
@@ -395,7 +417,15 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
         yf = rint(__dmul_rn(gg.y, p.theta));
       } else {
         const float4 qg = reinterpret_cast<const float4 *>(squad)[j];
-        const float2 rg = reinterpret_cast<const float2 *>(sres)[j];
+        float2 rg = reinterpret_cast<const float2 *>(sres)[j];
+        if (kUpd && s == 0 && j < a.sv.n_vis) {                  // uniform source test
+          const float2 ao = sum_mixed(gg.x, gg.y, gg.z, u.old32, 0, u.n_old);
+          const float2 an = sum_mixed(gg.x, gg.y, gg.z, u.new32, 0, u.n_new);
+          const float sp = (float)gg.w;
+          rg = make_float2(fmaf(sp, ao.x, rg.x), fmaf(sp, ao.y, rg.y));
+          rg = make_float2(fmaf(-sp, an.x, rg.x), fmaf(-sp, an.y, rg.y));
+          reinterpret_cast<float2 *>(u.sv.res)[j] = rg;
+        }
         const SrcMixed p = a.src32[s];
         const double ph = fma(gg.x, p.l, fma(gg.y, p.m, gg.z * p.n1));
         const float tt = (float)__builtin_amdgcn_fract(ph);
@@ -495,18 +525,34 @@ int64_t chunk_size(int64_t n_vis, int64_t bpc, int64_t capacity) {
 
 }  // namespace
 
-hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st) {
+hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st, const UpdateArgs *upd) {
   const int ns = mixed ? kNsMixed : kNsF64;
   ExtractArgs a = a0;
   const Sorted &v = a.sv;
   const uint64_t *wt = reinterpret_cast<const uint64_t *>(v.wt);
+  // the update is fused only for one changed source (a serial refinement):
+  // more sources' sums in the first source's pass lengthen the extraction's
+  // latency-bound steps by more than the separate pass costs
+  const bool fuse = upd && a.n_src <= kVpSources && upd->n_old <= 1 && upd->n_new <= 1;
+  if (upd && !fuse) {
+    hipError_t e = launch_update_sorted(*upd, mixed, st);
+    if (e != hipSuccess) return e;
+  }
   if (a.n_src <= kVpSources) {
     const int64_t waves = (v.n_vis + 64 * kVpSteps - 1) / (64 * kVpSteps);
     const dim3 grid((unsigned)((waves + 3) / 4));
-    if (mixed)
-      hipLaunchKernelGGL(k_extract_vp<true>, grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell);
-    else
-      hipLaunchKernelGGL(k_extract_vp<false>, grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell);
+    UpdateArgs u = fuse ? *upd : UpdateArgs{};
+    if (fuse) {
+      if (mixed)
+        hipLaunchKernelGGL((k_extract_vp<true, true>), grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell, u);
+      else
+        hipLaunchKernelGGL((k_extract_vp<false, true>), grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell, u);
+    } else {
+      if (mixed)
+        hipLaunchKernelGGL((k_extract_vp<true, false>), grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell, u);
+      else
+        hipLaunchKernelGGL((k_extract_vp<false, false>), grid, dim3(256), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell, u);
+    }
     return hipGetLastError();
   }
   a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);

@@ -794,7 +794,7 @@ int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
 // into the sorted layout, then extract and compact; `vis` NULL: the sorted
 // layout already holds the residual (kept there by the caller), no gather.
 int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *vis, int subtract,
-                   rlf_facets *f) {
+                   rlf_facets *f, const UpdateArgs *upd) {
   if (!f || f->ctx != c) return fail(c, RLF_EINVAL, "facets is NULL or from another context");
   if (int e = check_obs(c, obs)) return e;
   if (obs->n_rows * obs->n_chan != f->sv.n_vis) return fail(c, RLF_EINVAL, "observation size differs from rlf_facets_create");
@@ -809,6 +809,7 @@ int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const
     f->model_key.swap(key);
   }
   hipError_t e = hipSuccess;
+  if (vis && upd) return fail(c, RLF_EINVAL, "a residual update applies to the kept sorted residual only");
   if (vis) {
     ResidualArgs ra{};
     ra.sv = f->sv;
@@ -836,7 +837,7 @@ int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const
   a.order = f->d_order;
   a.acc = f->acc;
   a.err = c->d_err;
-  e = launch_extract(a, f->mixed, c->stream);
+  e = launch_extract(a, f->mixed, c->stream, upd);
   if (e != hipSuccess) return hip_fail(c, e, "extract kernel launch");
   CompactArgs ca{};
   ca.n_src = (int32_t)f->n_src;
@@ -878,17 +879,18 @@ int sorted_residual(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *sky, cons
   return RLF_OK;
 }
 
-// R += (models of old_m) - (models of new_m) on the residual kept in the
-// sorted layout of f (and in rs for the FP64 form).
-int update_sorted_residual(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
-                           double2 *rs) {
+// Arguments of R += (models of old_m) - (models of new_m) on the residual
+// kept in the sorted layout of f (and in rs for the FP64 form); the two
+// model tables are uploaded into the context's two model slots.
+int prepare_update(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
+                   double2 *rs, UpdateArgs &u) {
   if (int e = check_cat(c, old_m, false)) return e;
   if (int e = check_cat(c, new_m, false)) return e;
   if (!f->mixed && !rs) return fail(c, RLF_EINVAL, "FP64 form needs the unweighted residual buffer");
   if (int e = set_device(c)) return e;
-  UpdateArgs u{};
-  // the two tables sit in the context's two model slots: the second lookup
-  // replaces the least recently used slot, never the one just returned
+  u = UpdateArgs{};
+  // the second lookup replaces the least recently used slot, never the one
+  // just returned
   if (int e = model_table(c, old_m, &u.old64, &u.old32)) return e;
   if (int e = model_table(c, new_m, &u.new64, &u.new32)) return e;
   if (u.old64 == u.new64 && cat_key(old_m) != cat_key(new_m))
@@ -897,7 +899,11 @@ int update_sorted_residual(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catal
   u.n_old = (int32_t)old_m->n_src;
   u.n_new = (int32_t)new_m->n_src;
   u.rs = f->mixed ? nullptr : rs;
-  hipError_t e = launch_update_sorted(u, f->mixed, c->stream);
+  return RLF_OK;
+}
+
+int update_sorted_residual(rlf_ctx *c, const UpdateArgs &u, int mixed) {
+  hipError_t e = launch_update_sorted(u, mixed, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "residual update kernel launch");
   return RLF_OK;
 }

@@ -272,7 +272,9 @@ struct FeatureArgs {
 
 // Launchers (enqueue on `st`; return the launch status).
 hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st);
-hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st);
+// upd (optional): first update the residual kept in the sorted layout for
+// changed source models (fused into the small-catalogue kernel).
+hipError_t launch_extract(const ExtractArgs &a, int mixed, hipStream_t st, const UpdateArgs *upd = nullptr);
 hipError_t launch_residual_sorted(const ResidualArgs &a, int mixed, hipStream_t st);
 hipError_t launch_update_sorted(const UpdateArgs &a, int mixed, hipStream_t st);
 hipError_t launch_sort_keys(const SortKeyArgs &a, hipStream_t st);

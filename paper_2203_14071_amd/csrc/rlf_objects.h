@@ -137,15 +137,19 @@ int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
 
 // Extraction into f: with `vis`, first the gather into f's sorted layout
 // (subtract = 1: minus f's own catalogue models); with vis NULL the sorted
-// layout already holds the residual.
+// layout already holds the residual, optionally after a pending update.
 int extract_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const void *vis, int subtract,
-                   rlf_facets *f);
+                   rlf_facets *f, const UpdateArgs *upd = nullptr);
 
 // A residual kept in the sorted layout of f (sequential refinement): set it
 // to obs.vis minus the models of `sky`, then update it as models change.
 // FP64 form: rs [n_vis] holds the unweighted residual next to sv.res = w R.
+// An update (prepare_update: the two model tables in the context's model
+// slots, valid until the next model-table lookup) is applied by its own pass
+// or, pending, by the next extraction (extract_facets(..., upd)).
 int sorted_residual(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *sky, const rlf_facets *f, double2 *rs);
-int update_sorted_residual(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
-                           double2 *rs);
+int prepare_update(rlf_ctx *c, const rlf_catalog *old_m, const rlf_catalog *new_m, const rlf_facets *f,
+                   double2 *rs, UpdateArgs &u);
+int update_sorted_residual(rlf_ctx *c, const UpdateArgs &u, int mixed);
 
 }  // namespace rlf

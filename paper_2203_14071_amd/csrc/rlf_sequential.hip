@@ -8,7 +8,9 @@
 // model, in sorted order), each chunk is extracted from it directly (no
 // gather) and fitted on the full grid, and the refined sources' models are
 // then swapped in place, R += (old models) - (new models), in one pass over
-// the sorted visibilities.  The arithmetic is that of the caller-order path
+// the sorted visibilities: the next chunk's extraction makes that pass
+// itself when it runs the small-catalogue kernel, otherwise the swap runs
+// before it.  The arithmetic is that of the caller-order path
 // (rlf_model_vis residual, accumulate and residual modes, then a gather), so
 // the results are the same.
 #include <hip/hip_runtime.h>
@@ -118,6 +120,9 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
   std::vector<uint32_t> flags((size_t)n, 0u);
   std::vector<double> he1((size_t)n), he2((size_t)n);
   rlf_facets *master = nullptr;
+  // the previous chunk's model swap, applied by the next extraction
+  UpdateArgs pending{};
+  bool has_pending = false;
   for (int64_t c0 = 0; c0 < n; c0 += chunk) {
     const int64_t c1 = std::min(n, c0 + chunk);
     std::vector<int64_t> idx;
@@ -138,7 +143,8 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
       master = f;
       if (int e = sorted_residual(c, obs, &cur, master, Rs)) return e;
     }
-    if (int e = extract_facets(c, obs, &v, nullptr, 0, f)) return e;
+    if (int e = extract_facets(c, obs, &v, nullptr, 0, f, has_pending ? &pending : nullptr)) return e;
+    has_pending = false;
     rlf_fit_out o = offset(*out, c0);
     if (int e = rlf_fit_sources(c, f, &full, &o)) return e;
     const size_t m = (size_t)(c1 - c0);
@@ -164,9 +170,12 @@ extern "C" int rlf_fit_sequential(rlf_ctx *c, const rlf_obs *obs, const rlf_cata
       }
       const SubCat new_m = subset(cat, good, e1, e2);
       const rlf_catalog vo = old_m.view(), vn = new_m.view();
-      if (int e = update_sorted_residual(c, &vo, &vn, master, Rs)) return e;
+      if (int e = prepare_update(c, &vo, &vn, master, Rs, pending)) return e;
+      has_pending = true;
     }
   }
+  if (has_pending)
+    if (int e = update_sorted_residual(c, pending, mixed ? 1 : 0)) return e;
 
   if (refit_bad) {
     std::vector<int64_t> bad;

@@ -27,12 +27,13 @@ def _field(n_src=8):
     return o, cat, vis
 
 
-@pytest.mark.parametrize("precision,chunk,n_src", [("fp64", 1, 8), ("fp64", 3, 8), ("fp64", 8, 8), ("mixed", 3, 8),
-                                                 ("fp64", 9, 20), ("mixed", 9, 20)])
+@pytest.mark.parametrize("precision,chunk,n_src", [("fp64", 1, 8), ("fp64", 3, 8), ("fp64", 8, 8), ("mixed", 1, 8),
+                                                 ("mixed", 3, 8), ("fp64", 9, 20), ("mixed", 9, 20)])
 def test_sequential_matches_oracle(precision, chunk, n_src):
-    """Chunks of 9 of 20 sources: the source-parallel extraction kernel for
-    the 9-source chunks (the second reusing the first chunk's facet object)
-    and the small-catalogue kernel for the last 2."""
+    """Chunks of 1 (the model swap fused into the next extraction), 3 and 8
+    (a separate swap pass), and 9 of 20 sources: the source-parallel
+    extraction kernel for the 9-source chunks (the second reusing the first
+    chunk's facet object) and the small-catalogue kernel for the last 2."""
     o, cat, vis = _field(n_src)
     mixed = precision == "mixed"
     n = cat.n_src

@@ -49,12 +49,12 @@ MODEL_FLOP_PAIR = 19
 # bracket) at this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (each
 # scaled by a plain copy's reading), for the kernels as they are now; None
 # where not measured.  profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md:
-#   extraction (k_extract): fetch 1712.0 / 1195.1 MB, write 1096.4 / 964.9 MB
+#   extraction (k_extract): fetch 1733.9 / 1192.4 MB, write 1096.4 / 983.3 MB
 #   likelihood (k_fit + k_estimate): fetch 154.8 + 150.2 / 78.9 + 150.0 MB,
 #     write 51.3 + 0.3 / 51.3 + 0.3 MB
-#   sky model (k_model): fetch 372.9 / 298.5 MB, write 148.3 / 74.1 MB
-TRAFFIC_BYTES = {"fp64": {"extract": 2808.4e6, "fit": 356.6e6, "model": 521.2e6},
-                 "mixed": {"extract": 2160.0e6, "fit": 280.5e6, "model": 372.6e6}}
+#   sky model (k_model): fetch 372.9 / 298.3 MB, write 148.3 / 74.1 MB
+TRAFFIC_BYTES = {"fp64": {"extract": 2830.3e6, "fit": 356.6e6, "model": 521.2e6},
+                 "mixed": {"extract": 2175.7e6, "fit": 280.5e6, "model": 372.4e6}}
 # VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Slots per unit of work are the VALU instructions of the compiled hot loop
 # at their measured gfx950 cost (FP64 and FP32 add/mul/FMA/round and FP32

@@ -569,3 +569,62 @@ def test_window_rule_brute_force_on_tiny_grid():
                                 and s[x * 21 + y] >= thr:
                             expect = True
         assert oracle.window_rejected(s, (a, b, c, d), S, p) == expect, trial
+
+
+# ---- facet sizing (Sec. 2.3) and the default scale prior (Sec. 2.2 Eq. 4, Sec. 2.4)
+
+# One arcsecond in radians, written out as a number (IAU: 1" = pi/648000 rad),
+# not computed by the oracle's own expression.
+RAD_PER_ARCSEC = 4.84813681109535993589914e-6
+
+
+def test_facet_theta_is_K_scale_lengths_in_radians():
+    """theta = K alpha with alpha converted to radians: a 1" source at K = 38
+    has a field of view of 38 arcsec = 1.8423e-4 rad, i.e. a cell of
+    1/theta = 5428 wavelengths.  Dropping the arcsec conversion, sizing the
+    facet by another width (a FWHM) or taking another K moves these numbers
+    far outside the tolerances."""
+    assert oracle.facet_theta(1.0, 38.0) == pytest.approx(38 * RAD_PER_ARCSEC, rel=1e-15)
+    assert oracle.facet_theta(1.0, 38.0) == pytest.approx(1.842291988216237e-4, rel=1e-13)
+    assert 1.0 / oracle.facet_theta(1.0, 38.0) == pytest.approx(5428.0, abs=0.5)
+    # numpy's own degree conversion as an independent route
+    for a, K in ((0.3, 38.0), (1.7, 38.0), (3.5, 20.0), (2.2, 100.0)):
+        assert oracle.facet_theta(a, K) == pytest.approx(K * np.deg2rad(a / 3600.0), rel=1e-14)
+    # the default K is the paper's 38 (Sec. 4.1)
+    assert oracle.facet_theta(1.3) == oracle.facet_theta(1.3, 38.0)
+
+
+def test_facet_cells_follow_theta():
+    """A visibility at u = (k + 0.4) / theta lands in cell k and one at
+    (k + 0.6) / theta in cell k + 1, so the cell width in wavelengths is the
+    inverse field of view of Sec. 2.3."""
+    alpha = 1.25
+    theta = oracle.facet_theta(alpha)
+    cell = 1.0 / (38 * alpha * RAD_PER_ARCSEC)
+    ks = np.array([-3, 0, 2, 7])
+    u = np.concatenate([(ks + 0.4) * cell, (ks + 0.6) * cell])
+    freq = np.array([oracle.C_LIGHT])                        # wavelength 1 m: metres = wavelengths
+    f = oracle.extract_facet(u, np.zeros_like(u), np.zeros_like(u), freq, np.ones_like(u),
+                             np.zeros(u.size, np.complex128), (0.0, 0.0, 0.0, alpha, 0.0, 0.0), theta)
+    assert sorted(f.ix.tolist()) == sorted(ks.tolist() + (ks + 1).tolist())
+    assert np.all(f.iy == 0) and np.all(f.count == 1)
+
+
+@pytest.mark.parametrize("flux_ujy", [10.0, 50.0, 200.0, 1000.0])
+def test_default_prior_median_follows_eq4(flux_ujy):
+    """With no per-source median, the scale prior is log-normal with median
+    e^ADD (S/uJy)^ESP (Eq. 4, written here in its power form) and width
+    R_STD = 0.3136 (Sec. 2.4), times the natural-spline quadrature weights;
+    against scipy's lognorm and CubicSpline.  A flux taken in Jy instead of
+    uJy, ADD and ESP swapped, or the median of another relation fails."""
+    from scipy.stats import lognorm
+    knots = oracle.alpha_knots(0.3, 3.5, 20)
+    got = oracle.log_alpha_weights([flux_ujy * 1e-6], knots)[0]
+    median = math.exp(-0.93) * flux_ujy ** 0.33
+    c = np.array([scipy.interpolate.CubicSpline(knots, np.eye(20)[k], bc_type="natural").integrate(0.3, 3.5)
+                  for k in range(20)])
+    ref = np.log(c) + lognorm(0.3136, scale=median).logpdf(knots)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+    # the prior peaks (in ln alpha) at the median: the knot nearest it carries the largest prior density x alpha
+    dens = got - np.log(c) + np.log(knots)
+    assert abs(math.log(knots[int(np.argmax(dens))]) - math.log(median)) <= np.max(np.diff(np.log(knots)))

@@ -103,10 +103,10 @@ __global__ __launch_bounds__(256) void k_write(CompactArgs a) {
       a.cells.vre[o] = vr;
       a.cells.vim[o] = vi;
       const double uc = (double)ix / theta, vc = (double)iy / theta;
-      if (kMixed)
-        a.cells.fit32[o] = make_float4((float)uc, (float)vc, (float)W, (float)(W * vr));
-      else
-        a.cells.fit64[o] = make_double4(uc, vc, W, W * vr);
+      // the mixed form's fit runs on the FP32 records; its estimator
+      // rechecks the points at its decisions on the FP64 ones
+      if (kMixed) a.cells.fit32[o] = make_float4((float)uc, (float)vc, (float)W, (float)(W * vr));
+      a.cells.fit64[o] = make_double4(uc, vc, W, W * vr);
     }
     out += total;
   }

@@ -4,6 +4,15 @@
 // covariance (weights exp(ln L - ln Lmax)), and the flags: bad variance,
 // empty facet, maximum on an edge of the evaluated region.  One block per
 // source; three passes over the source's grid values with block reductions.
+//
+// The set is cut at a threshold and the maximum is a comparison, so the
+// estimate is discontinuous in ln L: a point within the arithmetic error of
+// the threshold can go either way.  In the mixed form (ln L summed in FP32,
+// error bounded by delta) every point within 2 delta of the threshold or
+// below the maximum is evaluated again in FP64 first, so both decisions are
+// those of FP64 arithmetic on the same facet; the weights of the other
+// points keep their FP32-summed values.
+#include "rlf_devmath.h"
 #include "rlf_internal.h"
 
 namespace rlf {
@@ -11,6 +20,61 @@ namespace rlf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
+
+// ln L(e) of source s at (e1, e2) in FP64, evaluated by one whole wave (all
+// 64 lanes, uniform arguments): the lanes split the source's cells, knots in
+// groups of four; per knot D and M are summed per lane and then across the
+// wave, and ln L(e) = ln sum_k w_k L(e, alpha_k) as in the FP64 fit (the
+// same terms, summed in another order).  Every lane returns the same value.
+__device__ double loglike_f64_wave(const EstimateArgs &a, int s, double e1, double e2) {
+  const int lane = threadIdx.x & 63;
+  const double det = 1.0 - e1 * e1 - e2 * e2;
+  const double g = 1.0 / (det * det);
+  const double a11 = 1.0 + e1, a12 = e2, a22 = 1.0 - e1;
+  const int64_t c0 = a.offsets[s], c1 = a.offsets[s + 1];
+  const double *lw = a.logw + (int64_t)s * a.num_r;
+  double mx = -INFINITY, acc = 0.0;
+  for (int k0 = 0; k0 < a.num_r; k0 += 4) {
+    double D[4], M[4], sk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      D[k] = M[k] = 0.0;
+      sk[k] = k0 + k < a.num_r ? a.sk[k0 + k] * g : 0.0;
+    }
+    for (int64_t c = c0 + lane; c < c1; c += 64) {
+      const double4 cl = a.fit64[c];
+      const double ku = fma(a11, cl.x, a12 * cl.y);
+      const double kv = fma(a12, cl.x, a22 * cl.y);
+      const double q = fma(ku, ku, kv * kv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double f = pow_m32_f64(fma(sk[k], q, 1.0));         // (2/3) f_c
+        D[k] = fma(cl.w, f, D[k]);
+        M[k] = fma(cl.z * f, f, M[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) {
+        D[k] += __shfl_xor(D[k], d);
+        M[k] += __shfl_xor(M[k], d);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k0 + k < a.num_r) {
+        // D and M carry (2/3) and (4/9) of their values: ln M is off by -2 ln(3/2)
+        const double v = lw[k0 + k] + (D[k] * D[k] / (2.0 * M[k]) - 0.5 * log(M[k]) - kLnPowM32Scale);
+        const double nm = fmax(mx, v);
+        acc = (mx > -INFINITY ? acc * exp(mx - nm) : 0.0) + exp(v - nm);
+        mx = nm;
+      }
+    }
+  }
+  return mx + log(acc);
+}
 
 __device__ __forceinline__ double block_sum(double x, double *sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -42,10 +106,90 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
   __shared__ int touch;
   const int s = blockIdx.x;
   if (a.redo && !a.redo[s]) return;
-  const double *L = a.lsurf + (int64_t)s * a.n_valid;
+  double *L = a.lsurf + (int64_t)s * a.n_valid;
   const int64_t n_cells = a.offsets[s + 1] - a.offsets[s];
   const uint32_t extra = a.redo ? (uint32_t)RLF_FLAG_FALLBACK : 0u;
   const int ctr = (a.n_e - 1) / 2;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+
+  // pass 1: maximum, smallest index on ties (each thread scans increasing j)
+  double best;
+  int bi;
+  auto find_max = [&]() {
+    best = -INFINITY;
+    bi = 0x7fffffff;
+    if (n_cells > 0) {
+      for (int j = threadIdx.x; j < a.n_valid; j += kThreads) {
+        const double v = L[j];
+        if (a.window) {
+          const int f = a.epts[j];
+          const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+          if (!in_box(a.window, s, i1, i2)) continue;
+        }
+        if (v > best) {
+          best = v;
+          bi = j;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const double ov = __shfl_xor(best, d);
+      const int oi = __shfl_xor(bi, d);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      shv[wid] = best;
+      shi[wid] = bi;
+    }
+    __syncthreads();
+    best = shv[0];
+    bi = shi[0];
+    for (int q = 1; q < 4; ++q)
+      if (shv[q] > best || (shv[q] == best && shi[q] < bi)) {
+        best = shv[q];
+        bi = shi[q];
+      }
+    __syncthreads();
+  };
+  find_max();
+
+  // FP64 recheck (mixed form): the points that can decide the maximum or sit
+  // at the threshold, each evaluated by a whole wave; the waves own disjoint
+  // points, and every read of a point's FP32-summed value precedes its write
+  if (a.fit64 && best > -INFINITY) {
+    const double delta = a.recheck_rel * (fabs(best) + a.recheck_abs);
+    const double lo = best - 2.0 * delta, thr0 = best + a.log_frac;
+    const bool lat_out = a.redo_out && a.check_stride > 0;
+    for (int j0 = wid * 64; j0 < a.n_valid; j0 += kThreads) {
+      const int j = j0 + lane;
+      bool cand = false;
+      if (j < a.n_valid) {
+        const double v = L[j];
+        const int f = a.epts[j];
+        const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+        if (in_box(a.window, s, i1, i2))
+          cand = v >= lo || fabs(v - thr0) <= 2.0 * delta;
+        else if (lat_out && (i1 - ctr) % a.check_stride == 0 && (i2 - ctr) % a.check_stride == 0)
+          cand = fabs(v - thr0) <= 2.0 * delta;
+      }
+      uint64_t m = __ballot(cand);
+      while (m) {
+        const int b = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int f = a.epts[j0 + b];
+        const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
+        const double v = loglike_f64_wave(a, s, (double)(i1 - ctr) * a.e_step, (double)(i2 - ctr) * a.e_step);
+        if (lane == 0) L[j0 + b] = v;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    find_max();
+  }
 
   if (a.surface) {
     double *S = a.surface + (int64_t)s * a.n_e * a.n_e;
@@ -59,47 +203,6 @@ __global__ __launch_bounds__(kThreads) void k_estimate(EstimateArgs a) {
       S[f] = (n_cells > 0 && in_box(a.window, s, i1, i2)) ? L[j] : -INFINITY;
     }
   }
-
-  // pass 1: maximum, smallest index on ties (each thread scans increasing j)
-  double best = -INFINITY;
-  int bi = 0x7fffffff;
-  if (n_cells > 0) {
-    for (int j = threadIdx.x; j < a.n_valid; j += kThreads) {
-      const double v = L[j];
-      if (a.window) {
-        const int f = a.epts[j];
-        const int i1 = f / a.n_e, i2 = f - i1 * a.n_e;
-        if (!in_box(a.window, s, i1, i2)) continue;
-      }
-      if (v > best) {
-        best = v;
-        bi = j;
-      }
-    }
-  }
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    const double ov = __shfl_xor(best, d);
-    const int oi = __shfl_xor(bi, d);
-    if (ov > best || (ov == best && oi < bi)) {
-      best = ov;
-      bi = oi;
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    shv[wid] = best;
-    shi[wid] = bi;
-  }
-  __syncthreads();
-  best = shv[0];
-  bi = shi[0];
-  for (int q = 1; q < 4; ++q)
-    if (shv[q] > best || (shv[q] == best && shi[q] < bi)) {
-      best = shv[q];
-      bi = shi[q];
-    }
-  __syncthreads();
 
   if (!(best > -INFINITY)) {                   // empty facet or nothing evaluated
     if (threadIdx.x == 0) {

@@ -24,6 +24,15 @@ constexpr int kVersion = 100;                   // 0.1.0
 constexpr int kMaxFacetHalf = 16383;            // side*side stays below 2^31
 constexpr int kSortedPad = 64;                  // zero-weight tail of the sorted arrays
 constexpr int kMaxRefineLevel = 12;             // finest refinement step e_step / 4096
+// Bound on the mixed form's ln L error, delta = kRecheckRel (|ln Lmax| +
+// kRecheckAbs), used to pick the points its estimator re-evaluates in FP64.
+// FP32 terms summed in blocks of 32 cells into FP64 carry a relative error of
+// a few ulp of the largest terms; the error measured against the FP64 form
+// on the 1000-source SKA-MID-like field is at most 18 * 2^-24 |ln Lmax|, and
+// 2^-16 leaves a factor 14 over it.  The offset covers the -ln(M)/2 part of
+// ln L (|ln M| / 2 < 64 for any M in e^[-128, 128]).
+constexpr double kRecheckRel = 1.0 / 65536.0;
+constexpr double kRecheckAbs = 64.0;
 
 }  // namespace
 
@@ -670,11 +679,8 @@ int create_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, const 
     if ((rc = dalloc(c, &f->cells.wsum, total))) break;
     if ((rc = dalloc(c, &f->cells.vre, total))) break;
     if ((rc = dalloc(c, &f->cells.vim, total))) break;
-    if (f->mixed) {
-      if ((rc = dalloc(c, &f->cells.fit32, total))) break;
-    } else {
-      if ((rc = dalloc(c, &f->cells.fit64, total))) break;
-    }
+    if (f->mixed && (rc = dalloc(c, &f->cells.fit32, total))) break;
+    if ((rc = dalloc(c, &f->cells.fit64, total))) break;
     if ((rc = dalloc(c, &f->d_logw, f->n_src * c->p.num_r))) break;
     if ((rc = dalloc(c, &f->d_lsurf, f->n_src * (int64_t)c->n_valid))) break;
     if ((rc = dalloc(c, &f->d_redo, f->n_src))) break;
@@ -761,11 +767,8 @@ int retarget_facets(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, rlf_
       if ((rc = dalloc(c, &f->cells.wsum, total))) break;
       if ((rc = dalloc(c, &f->cells.vre, total))) break;
       if ((rc = dalloc(c, &f->cells.vim, total))) break;
-      if (f->mixed) {
-        if ((rc = dalloc(c, &f->cells.fit32, total))) break;
-      } else {
-        if ((rc = dalloc(c, &f->cells.fit64, total))) break;
-      }
+      if (f->mixed && (rc = dalloc(c, &f->cells.fit32, total))) break;
+      if ((rc = dalloc(c, &f->cells.fit64, total))) break;
     } while (0);
     if (rc != RLF_OK) return rc;                       // the object stays unusable until freed
     f->dense_cap = total;
@@ -1193,6 +1196,14 @@ int enqueue_fit(rlf_ctx *c, const rlf_facets *f, const rlf_fit_opts &o, const rl
   ea.n_above = out.n_above;
   ea.flags = out.flags;
   ea.surface = o.want_surface ? out.surface : nullptr;
+  if (f->mixed && f->pos_side <= 1) {
+    ea.fit64 = f->cells.fit64;
+    ea.sk = c->d_sk;
+    ea.logw = f->d_logw;
+    ea.num_r = c->p.num_r;
+    ea.recheck_rel = kRecheckRel;
+    ea.recheck_abs = kRecheckAbs;
+  }
   hipError_t e;
   if (queue && !windowed)
     e = launch_fit_queue(fa, *queue, f->mixed, queue_blocks, c->stream);

@@ -235,7 +235,7 @@ struct EstimateArgs {
   double bad_sigma, bad_sqrtdet;
   const int32_t *epts;
   const int64_t *offsets;
-  const double *lsurf;
+  double *lsurf;             // written only by the FP64 recheck below
   const int32_t *window;     // null = full grid
   const int32_t *redo;       // fallback pass: only these sources; null = all
   int32_t *redo_out;         // windowed pass with fallback: set where the window is not trusted
@@ -244,6 +244,18 @@ struct EstimateArgs {
   int32_t *argmax, *n_above;
   uint32_t *flags;
   double *surface;           // [n_src*n_e*n_e] or null
+  // Mixed form, position fixed: the decisions of the estimate (the maximum
+  // and membership of the thresholded set) are taken on FP64 values.  With
+  // delta = recheck_rel * (|max| + recheck_abs), a bound on the error of the
+  // FP32-summed ln L, every evaluated point within 2 delta below the maximum
+  // or within 2 delta of the threshold is evaluated again in FP64 from the
+  // FP64 cell records before the maximum and the set are taken; null fit64 =
+  // no recheck (FP64 form).
+  const double4 *fit64;
+  const double *sk;          // [num_r] 4 pi^2 alpha_k^2
+  const double *logw;        // [n_src*num_r]
+  int32_t num_r;
+  double recheck_rel, recheck_abs;
 };
 
 // C[M x N] (FP32, row stride ldc) = A * B, A(m, k) = a[m*sam + k*sak],

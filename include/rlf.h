@@ -52,7 +52,9 @@ typedef enum {
   RLF_ENOMEM = -2,        /* device or host allocation failed                          */
   RLF_EDEVICE = -3,       /* a HIP runtime call failed; rlf_last_error() has its text  */
   RLF_ERANGE = -4,        /* a facet or the visibility count exceeds supported sizes  */
-  RLF_EUNSUPPORTED = -5   /* valid request the library does not implement              */
+  RLF_EUNSUPPORTED = -5,  /* valid request the library does not implement              */
+  RLF_EIO = -6            /* a file could not be opened, read or written, or is not a  */
+                          /* checkpoint of this network (rlf_last_error() says which)  */
 } rlf_status;
 
 typedef enum { RLF_FP64 = 0, RLF_MIXED = 1 } rlf_precision;
@@ -390,6 +392,25 @@ int rlf_mlp_set_state(rlf_mlp *net, const float *params, const float *adam_m, co
 /* Copy parameters, Adam moments and the last gradients to host arrays
  * [n_params] (any may be NULL) and the step count.  Synchronises. */
 int rlf_mlp_get_state(rlf_mlp *net, float *params, float *adam_m, float *adam_v, float *grad, int64_t *step);
+
+/* Checkpoint of the training state: FP32 master parameters, Adam moments m
+ * and v, and the step count (everything rlf_mlp_train_step reads besides its
+ * arguments), written to the file at path (host string).  Format, little-
+ * endian: the 8 bytes "RLFMLP01", uint32 format version 1, uint32 0, int64
+ * n_params, int64 step, uint64 FNV-1a hash of the payload, then the payload
+ * params, m, v as FP32 [n_params] each.  The file is written under a
+ * temporary name in the same directory and renamed over path when complete,
+ * so a failed save leaves any earlier file at path intact.  Synchronises.
+ * RLF_EIO if the file cannot be written. */
+int rlf_mlp_save(rlf_mlp *net, const char *path);
+
+/* Restore a checkpoint written by rlf_mlp_save: the network's parameters,
+ * Adam moments and step become the file's, so that training continues bit
+ * for bit as it would have from the saved state.  The file is read and
+ * checked (header, size, payload hash) before anything is changed: on
+ * RLF_EIO (unreadable, truncated, another format or network size, hash
+ * mismatch) the network keeps its state.  Synchronises. */
+int rlf_mlp_load(rlf_mlp *net, const char *path);
 
 /* Network inputs of every source of the last extraction: device BF16
  * [n_src x 8192], Vbar / (S g) with g the mean over the observation's

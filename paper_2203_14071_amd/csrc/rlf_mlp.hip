@@ -3,8 +3,11 @@
 // Parameter layout (FP32, contiguous): W1 [8192 x 512], b1 [512],
 // W2 [512 x 512], b2, W3 [512 x 512], b3, W4 [512 x 6], b4 [6].
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "rlf_objects.h"
@@ -202,6 +205,105 @@ int rlf_mlp_get_state(rlf_mlp *n, float *params_host, float *m_host, float *v_ho
   if (grad_host) HIPCHK(c, hipMemcpy(grad_host, n->g, sizeof(float) * kParams, hipMemcpyDeviceToHost));
   if (step) *step = n->step;
   return RLF_OK;
+}
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'R', 'L', 'F', 'M', 'L', 'P', '0', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t reserved;
+  int64_t n_params;
+  int64_t step;
+  uint64_t hash;
+};
+static_assert(sizeof(CkptHeader) == 40, "checkpoint header layout");
+
+// FNV-1a, 64 bit (offset basis 14695981039346656037, prime 1099511628211).
+uint64_t fnv1a(const void *data, size_t n, uint64_t h) {
+  const unsigned char *p = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t payload_hash(const std::vector<float> &buf) {
+  return fnv1a(buf.data(), buf.size() * sizeof(float), 14695981039346656037ull);
+}
+
+}  // namespace
+
+int rlf_mlp_save(rlf_mlp *n, const char *path) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  c->err.clear();
+  if (!path || !*path) return fail(c, RLF_EINVAL, "rlf_mlp_save: path is NULL or empty");
+  std::vector<float> buf;
+  try {
+    buf.resize(3 * (size_t)kParams);
+  } catch (...) {
+    return fail(c, RLF_ENOMEM, "rlf_mlp_save: host buffer");
+  }
+  int64_t step = 0;
+  if (int e = rlf_mlp_get_state(n, buf.data(), buf.data() + kParams, buf.data() + 2 * kParams, nullptr, &step))
+    return e;
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.n_params = kParams;
+  h.step = step;
+  h.hash = payload_hash(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *fp = std::fopen(tmp.c_str(), "wb");
+  if (!fp) return fail(c, RLF_EIO, "rlf_mlp_save: cannot open " + tmp + ": " + std::strerror(errno));
+  const bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 &&
+                  std::fwrite(buf.data(), sizeof(float), buf.size(), fp) == buf.size() && std::fflush(fp) == 0;
+  const bool closed = std::fclose(fp) == 0;
+  if (!ok || !closed) {
+    std::remove(tmp.c_str());
+    return fail(c, RLF_EIO, "rlf_mlp_save: write to " + tmp + " failed");
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(c, RLF_EIO, std::string("rlf_mlp_save: cannot rename onto ") + path + ": " + std::strerror(errno));
+  }
+  return RLF_OK;
+}
+
+int rlf_mlp_load(rlf_mlp *n, const char *path) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  c->err.clear();
+  if (!path || !*path) return fail(c, RLF_EINVAL, "rlf_mlp_load: path is NULL or empty");
+  FILE *fp = std::fopen(path, "rb");
+  if (!fp) return fail(c, RLF_EIO, std::string("rlf_mlp_load: cannot open ") + path + ": " + std::strerror(errno));
+  CkptHeader h{};
+  std::vector<float> buf;
+  std::string why;
+  if (std::fread(&h, sizeof h, 1, fp) != 1) why = "file shorter than the header";
+  else if (std::memcmp(h.magic, kCkptMagic, 8) != 0) why = "not a network checkpoint (magic)";
+  else if (h.version != kCkptVersion) why = "format version " + std::to_string(h.version);
+  else if (h.n_params != kParams) why = "parameter count " + std::to_string(h.n_params) + " of another network";
+  else if (h.step < 0) why = "negative step count";
+  if (why.empty()) {
+    try {
+      buf.resize(3 * (size_t)kParams);
+    } catch (...) {
+      std::fclose(fp);
+      return fail(c, RLF_ENOMEM, "rlf_mlp_load: host buffer");
+    }
+    if (std::fread(buf.data(), sizeof(float), buf.size(), fp) != buf.size()) why = "payload truncated";
+    else if (std::fgetc(fp) != EOF) why = "bytes after the payload";
+    else if (payload_hash(buf) != h.hash) why = "payload hash mismatch";
+  }
+  std::fclose(fp);
+  if (!why.empty()) return fail(c, RLF_EIO, std::string("rlf_mlp_load: ") + path + ": " + why);
+  return rlf_mlp_set_state(n, buf.data(), buf.data() + kParams, buf.data() + 2 * kParams, h.step);
 }
 
 int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlf.so")
 
-RLF_OK, RLF_EINVAL, RLF_ENOMEM, RLF_EDEVICE, RLF_ERANGE, RLF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RLF_OK, RLF_EINVAL, RLF_ENOMEM, RLF_EDEVICE, RLF_ERANGE, RLF_EUNSUPPORTED, RLF_EIO = 0, -1, -2, -3, -4, -5, -6
 RLF_FP64, RLF_MIXED = 0, 1
 RLF_FLAG_BAD_VAR, RLF_FLAG_EMPTY, RLF_FLAG_EDGE, RLF_FLAG_FALLBACK, RLF_FLAG_REFIT, RLF_FLAG_REFINED = 1, 2, 4, 8, 16, 32
 RLF_MODEL_WRITE, RLF_MODEL_ACCUMULATE, RLF_MODEL_RESIDUAL = 0, 1, 2
@@ -92,6 +92,8 @@ _SIGNATURES = {
     "rlf_mlp_free": ([_c_vp], ctypes.c_int),
     "rlf_mlp_set_state": ([_c_vp, _c_vp, _c_vp, _c_vp, ctypes.c_int64], ctypes.c_int),
     "rlf_mlp_get_state": ([_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_lp], ctypes.c_int),
+    "rlf_mlp_save": ([_c_vp, ctypes.c_char_p], ctypes.c_int),
+    "rlf_mlp_load": ([_c_vp, ctypes.c_char_p], ctypes.c_int),
     "rlf_mlp_features": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
     "rlf_mlp_forward": ([_c_vp, _c_vp, ctypes.c_int64, _c_vp], ctypes.c_int),
     "rlf_mlp_train_step": ([_c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_float, _c_vp], ctypes.c_int),
@@ -405,6 +407,14 @@ class Mlp:
                                                 _np_ptr(out["v"]), _np_ptr(out["grad"]), ctypes.byref(st)))
         out["step"] = st.value
         return out
+
+    def save(self, path):
+        """Checkpoint (parameters, Adam moments, step) to a file (rlf_mlp_save)."""
+        self.ctx._check(lib().rlf_mlp_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        """Restore a checkpoint written by save (rlf_mlp_load)."""
+        self.ctx._check(lib().rlf_mlp_load(self.h, os.fsencode(path)))
 
     def features(self, facets: "Facets", x):
         return self.ctx._check(lib().rlf_mlp_features(self.ctx.h, facets.h, _ptr(x)))

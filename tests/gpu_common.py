@@ -138,3 +138,63 @@ def fit_out_tensors(n_src, n_e=81, surface=True):
 
 def host(out):
     return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+# ---- estimate parity with threshold decisions accounted for ------------------
+
+def mixed_delta(lmax):
+    """Error bound of the mixed form's ln L against the FP64 oracle on the
+    same inputs: delta = 2^-16 (|ln Lmax| + 64), the bound the library's
+    mixed estimator uses to pick the points it re-evaluates in FP64 (FP32
+    terms summed in blocks of 32 cells into FP64 carry a relative error of a
+    few ulp of the largest terms; 18 * 2^-24 |ln Lmax| was the largest
+    measured against the FP64 form on the 1000-source field)."""
+    return (abs(lmax) + 64.0) / 65536.0
+
+
+def check_estimate_matched(gpu, s, surf_o, surf_g, ll_tol, flip_band, e_tol, est_o=None):
+    """One source's estimate against the oracle's, the discontinuity of the
+    5 % cut accounted for.
+
+    surf_o: the oracle's ln L over the flattened grid, -inf where not
+    evaluated; it must hold every point within flip_band below the oracle's
+    threshold (the full surface, or the stored points of a golden file).
+    surf_g: the GPU's surface.  Checked: |dl| <= ll_tol at every finite
+    oracle point and at the maximum; the GPU's set {surf_g >= its max + ln
+    0.05} differs from the oracle's only at points within flip_band of the
+    oracle's threshold, and holds nothing outside surf_o's finite points;
+    the argmax differs only between points within flip_band of the maximum;
+    the GPU's e, sigma and covariance equal, to e_tol, the oracle's
+    estimator applied to the oracle's values on the GPU's set.  Returns (raw
+    max |de| against est_o, max |de| over the same set, max |dl| / ll_tol,
+    whether a point changed sides)."""
+    i1, i2, e1g, e2g, valid = oracle.e_grid(81, 0.02)
+    if est_o is None:
+        est_o = oracle.estimate(surf_o, e1g, e2g, valid, 81)
+    fin = valid & np.isfinite(surf_o)
+    tol = ll_tol(surf_o[fin], est_o.lmax)
+    dl = np.abs(surf_g[fin] - surf_o[fin])
+    assert np.all(dl <= tol), (s, float(np.max(dl / tol)))
+    assert abs(gpu["lmax"][s] - est_o.lmax) <= ll_tol(np.array([est_o.lmax]), est_o.lmax)[0], s
+    thr_o = est_o.lmax + math.log(0.05)
+    mem_o = fin & (surf_o >= thr_o)
+    mem_g = valid & np.isfinite(surf_g) & (surf_g >= gpu["lmax"][s] + math.log(0.05))
+    assert int(gpu["n_above"][s]) == int(np.count_nonzero(mem_g)), s
+    assert not np.any(mem_g & ~fin), s                       # no member the oracle did not see
+    diff = mem_o != mem_g
+    flipped = bool(np.any(diff))
+    if flipped:
+        assert np.all(np.abs(surf_o[diff] - thr_o) <= flip_band(est_o.lmax)), (s, surf_o[diff] - thr_o)
+    am = int(gpu["argmax"][s])
+    if am != est_o.argmax:
+        assert fin[am] and est_o.lmax - surf_o[am] <= flip_band(est_o.lmax), s
+    adj = np.where(mem_g, surf_o, -np.inf)
+    est = oracle.estimate(adj, e1g, e2g, valid, 81, frac=1e-300)
+    d_adj = max(abs(gpu[k][s] - getattr(est, k)) for k in ("e1", "e2", "s1", "s2", "c12"))
+    assert d_adj <= e_tol, (s, d_adj)
+    if am == est.argmax:
+        assert int(gpu["flags"][s]) & ~rlf.RLF_FLAG_FALLBACK == est.flags, s
+    raw = max(abs(gpu["e1"][s] - est_o.e1), abs(gpu["e2"][s] - est_o.e2))
+    if not flipped:
+        assert raw <= e_tol, (s, raw)
+    return raw, d_adj, float(np.max(dl / tol)) if dl.size else 0.0, flipped

@@ -73,6 +73,7 @@ def test_extraction_and_fit_sampled_sources(field):
     ctx.fit_sources(f, lat, mode=2, check_stride=4)
     ctx.sync()
     hl = G.host(lat)
+    n_lattice = 0
     for s in pick:
         ref = G.oracle_facet(o, nz, cat, s)
         G.check_facet(fac, s, ref, scale, cat.flux_jy[s])
@@ -81,6 +82,7 @@ def test_extraction_and_fit_sampled_sources(field):
         d = 12 * G.LL_RTOL * max(1.0, abs(est.lmax))
         wins = {oracle.lattice_window(surf, 4, oracle.Params(frac=0.05 * np.exp(x))) for x in (0.0, -d, d)}
         if len(wins) == 1:
+            n_lattice += 1
             lsurf, _, refit = oracle.lattice_narrowed_fit(ref, cat.flux_jy[s], 4)
             assert bool(hl["flags"][s] & rlf.RLF_FLAG_FALLBACK) == refit, s
             variants = G.oracle_estimate_variants(lsurf)
@@ -88,6 +90,9 @@ def test_extraction_and_fit_sampled_sources(field):
                 for e in variants:
                     e.flags |= rlf.RLF_FLAG_FALLBACK
             G.check_fit(hl, s, lsurf, variants)
+    # the lattice-seeded window is compared wherever moving the threshold by
+    # a few LL_RTOL leaves it unchanged: at least one sampled source
+    assert n_lattice >= 1
     f.free()
 
 
@@ -109,6 +114,7 @@ def test_position_marginalised_fit_and_refinement_sampled_sources(field):
     ctx.sync()
     hr = G.host(out)
     a = cat.alpha_arcsec
+    n_refined = 0
     for s in sorted({int(np.argmin(a)), 137}):
         ref = G.oracle_facet(o, nz, cat, s)
         surf, est = fit_source_pos(ref, cat.flux_jy[s], 3, 0.2)
@@ -123,7 +129,9 @@ def test_position_marginalised_fit_and_refinement_sampled_sources(field):
         r = runs[0]
         if int(h["n_above"][s]) == est.n_above and all(
                 q.n_above == r.n_above and q.flags == r.flags for q in runs[1:]):
+            n_refined += 1
             assert int(hr["flags"][s]) == r.flags and int(hr["n_above"][s]) == r.n_above
             for k in ("e1", "e2", "s1", "s2"):
                 assert abs(hr[k][s] - getattr(r, k)) <= G.E_TOL, (s, k)
+    assert n_refined >= 1
     f.free()

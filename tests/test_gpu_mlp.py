@@ -10,6 +10,7 @@ roundings by one BF16 step (2^-8 relative).  Outputs and gradient blocks are
 therefore compared in relative L2 norm (1e-3), and the fraction of elements
 off by more than a few BF16 steps is bounded."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -183,6 +184,61 @@ def test_training_reduces_loss_and_resumes_bit_exactly(ctx):
     a, c = net.get_state(), net2.get_state()
     assert np.array_equal(a["params"], c["params"]) and np.array_equal(a["m"], c["m"])
     assert a["step"] == c["step"] == 65
+    net.free()
+    net2.free()
+
+
+def test_checkpoint_file_resumes_bit_exactly(ctx, tmp_path):
+    """rlf_mlp_save / rlf_mlp_load: train, save to a file, train on; a new
+    network loaded from the file and trained on the same batches ends with
+    identical parameters, moments and step.  Damaged or foreign files are
+    refused with RLF_EIO and leave the network's state unchanged."""
+    torch = G.torch_cuda()
+    rng = np.random.default_rng(21)
+    n = 512
+    t = rng.standard_normal((n, 3)) * 0.3
+    x = M.bf16(t @ (rng.standard_normal((3, M.N_IN)) * 0.05) + 0.01 * rng.standard_normal((n, M.N_IN)))
+    xd = _bf16_tensor(x)
+    td = torch.from_numpy(t.astype(np.float32)).to("cuda:0")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    net = rlf.Mlp(ctx, max_batch=128)
+    net.set_state(M.pack(_init(22)))
+    for step in range(12):
+        net.train_step(xd[(step % 4) * 128:(step % 4 + 1) * 128], td[(step % 4) * 128:(step % 4 + 1) * 128], 1e-3, loss)
+    path = str(tmp_path / "net.ckpt")
+    net.save(path)
+    saved = net.get_state()
+    assert os.path.getsize(path) == 40 + 3 * 4 * net.n_params
+    assert not os.path.exists(path + ".tmp")
+    for step in range(12, 19):
+        net.train_step(xd[(step % 4) * 128:(step % 4 + 1) * 128], td[(step % 4) * 128:(step % 4 + 1) * 128], 1e-3, loss)
+    net2 = rlf.Mlp(ctx, max_batch=128)
+    net2.load(path)
+    st2 = net2.get_state()
+    for k in ("params", "m", "v"):
+        assert np.array_equal(st2[k], saved[k]), k
+    assert st2["step"] == saved["step"] == 12
+    for step in range(12, 19):
+        net2.train_step(xd[(step % 4) * 128:(step % 4 + 1) * 128], td[(step % 4) * 128:(step % 4 + 1) * 128], 1e-3, loss)
+    a, b = net.get_state(), net2.get_state()
+    for k in ("params", "m", "v"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["step"] == b["step"] == 19
+    # damaged files: the loading network keeps its state
+    raw = open(path, "rb").read()
+    bad = {"truncated": raw[:-4], "flipped": raw[:1000] + bytes([raw[1000] ^ 1]) + raw[1001:],
+           "magic": b"XXXXXXXX" + raw[8:], "longer": raw + b"\0", "empty": b""}
+    for name, blob in bad.items():
+        p = str(tmp_path / f"{name}.ckpt")
+        open(p, "wb").write(blob)
+        with pytest.raises(rlf.RlfError) as ei:
+            net2.load(p)
+        assert ei.value.code == rlf.RLF_EIO, name
+    with pytest.raises(rlf.RlfError) as ei:
+        net2.load(str(tmp_path / "missing.ckpt"))
+    assert ei.value.code == rlf.RLF_EIO
+    c = net2.get_state()
+    assert np.array_equal(c["params"], b["params"]) and c["step"] == 19
     net.free()
     net2.free()
 

@@ -167,6 +167,23 @@ int rlf_alpha_from_flux(const double *flux_jy_host, int64_t n, double add, doubl
 int rlf_model_vis(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
                   int64_t src_begin, int64_t src_end, void *out, int mode);
 
+/* rlf_model_vis for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same computation and
+ * result, bit for bit, with the channel and source tables held in one
+ * fixed, library-owned device array per GPU (513 KiB, kept until the process
+ * ends) instead of memory the context allocates; no hipMalloc, hipFree or
+ * other allocating call is made (the host staging it copies from is
+ * allocated once by rlf_create).  At most 4096 sources per call
+ * (src_end - src_begin), else RLF_EINVAL; larger catalogues are summed in
+ * several calls with RLF_MODEL_ACCUMULATE.  The call first waits for the
+ * work already queued on the context's stream, then copies the tables and
+ * enqueues the kernel; RLF_EUNSUPPORTED while the stream is being captured.
+ * Every call on one GPU shares that GPU's array, whichever context makes
+ * it: calls on one GPU must not overlap (two contexts on two streams
+ * enqueuing at once race on the tables). */
+int rlf_model_vis_noalloc(rlf_ctx *ctx, const rlf_obs *obs, const rlf_catalog *cat,
+                          int64_t src_begin, int64_t src_end, void *out, int mode);
+
 /* Facet geometry for a catalogue on an observation (Sec. 2.3): per source
  * theta_s = K * alpha_s (alpha in radians, converted first), cell size
  * 1/theta_s, cells centred on the uv origin, half-size

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "rlf_objects.h"
@@ -186,6 +187,45 @@ SrcMixed to_mixed(const SrcModel &m) {
 
 constexpr size_t kPinnedRing = (size_t)8 << 20;   // bytes of the upload staging ring
 
+// Device memory of rlf_model_vis_noalloc: the channel table and the source
+// tables of at most kNoAllocMaxSources sources, in one file-scope array per
+// device (held until the process ends).  In host code `scratch` names a host
+// stand-in: the device address comes from hipGetSymbolAddress, resolved once
+// per device with that device current (rlf_create) and used everywhere the
+// host passes the array's memory on.
+constexpr int64_t kNoAllocMaxSources = 4096;
+constexpr size_t kNoAllocChanOff = 0;
+constexpr size_t kNoAllocSrcOff = 1024;                                         // >= sizeof(ChanTable)
+constexpr size_t kNoAllocSrc32Off = kNoAllocSrcOff + kNoAllocMaxSources * sizeof(SrcModel);
+constexpr size_t kNoAllocBytes = kNoAllocSrc32Off + kNoAllocMaxSources * sizeof(SrcMixed);
+static_assert(sizeof(ChanTable) <= kNoAllocSrcOff, "channel table does not fit its slot");
+static_assert(kNoAllocSrcOff % 256 == 0 && kNoAllocSrc32Off % 256 == 0, "table offsets must stay aligned");
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device`, resolved
+// on the first call for that device.
+int resolve_scratch(rlf_ctx *c, int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(c, RLF_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return RLF_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device] = ptr;
+  return RLF_OK;
+}
+
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 namespace rlf {
@@ -264,14 +304,19 @@ int model_table(rlf_ctx *c, const rlf_catalog *k, const SrcModel **out, const Sr
   return RLF_OK;
 }
 
-int chan_table(rlf_ctx *c, const rlf_obs *o) {
-  std::vector<double> key(o->freq_hz_host, o->freq_hz_host + o->n_chan);
-  if (c->d_chan && key == c->chan_key) return RLF_OK;
-  ChanTable h{};
+void fill_chan(const rlf_ctx *c, const rlf_obs *o, ChanTable &h) {
+  h = ChanTable{};
   for (int k = 0; k < o->n_chan; ++k) {
     h.scale[k] = o->freq_hz_host[k] / kC;
     h.spec[k] = std::pow(o->freq_hz_host[k] / c->p.ref_freq_hz, c->p.beta);
   }
+}
+
+int chan_table(rlf_ctx *c, const rlf_obs *o) {
+  std::vector<double> key(o->freq_hz_host, o->freq_hz_host + o->n_chan);
+  if (c->d_chan && key == c->chan_key) return RLF_OK;
+  ChanTable h{};
+  fill_chan(c, o, h);
   if (!c->d_chan)
     if (int e = dalloc(c, &c->d_chan, 1)) return e;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -470,6 +515,15 @@ int rlf_create(rlf_ctx **out, int device, void *hip_stream, const rlf_params *p)
       rc = RLF_EDEVICE;
       break;
     }
+    // rlf_model_vis_noalloc: the device's scratch address and a host staging
+    // buffer of the same size, made here so that the entry point allocates nothing
+    if ((rc = resolve_scratch(c, device))) break;
+    try {
+      c->noalloc_stage.resize(kNoAllocBytes);
+    } catch (...) {
+      rc = RLF_ENOMEM;
+      break;
+    }
   } while (0);
   if (rc != RLF_OK) {
     rlf_destroy(c);
@@ -554,6 +608,67 @@ int rlf_model_vis(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_
   a.src32 = d_src32;
   a.s_begin = (int32_t)src_begin;
   a.s_end = (int32_t)src_end;
+  a.vis_in = obs->vis;
+  a.out = out;
+  hipError_t e = launch_model(a, c->p.precision == RLF_MIXED, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "model kernel launch");
+  return RLF_OK;
+}
+
+int rlf_model_vis_noalloc(rlf_ctx *c, const rlf_obs *obs, const rlf_catalog *cat, int64_t src_begin,
+                          int64_t src_end, void *out, int mode) {
+  if (!c) return RLF_EINVAL;
+  c->err.clear();
+  if (int e = check_obs(c, obs)) return e;
+  if (int e = check_cat(c, cat, false)) return e;
+  if (!out) return fail(c, RLF_EINVAL, "out is NULL");
+  if (mode < 0 || mode > 2) return fail(c, RLF_EINVAL, "mode");
+  if (mode == RLF_MODEL_RESIDUAL && !obs->vis) return fail(c, RLF_EINVAL, "obs.vis is NULL");
+  if (src_begin < 0 || src_end > cat->n_src || src_begin > src_end) return fail(c, RLF_EINVAL, "source range");
+  const int64_t n = src_end - src_begin;
+  if (n > kNoAllocMaxSources)
+    return fail(c, RLF_EINVAL, "rlf_model_vis_noalloc: at most 4096 sources per call (its fixed scratch size)");
+  char *ptr = static_cast<char *>(scratch_ptr(c->device));
+  if (!ptr || c->noalloc_stage.size() < kNoAllocBytes)
+    return fail(c, RLF_EDEVICE, "rlf_model_vis_noalloc: scratch not resolved for this device");
+  if (int e = set_device(c)) return e;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(c, hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(c, RLF_EUNSUPPORTED, "rlf_model_vis_noalloc copies its tables from host memory: not under capture");
+  // the previous call's copy and kernels on this stream read the same
+  // scratch and staging memory: let them finish first
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  unsigned char *h = c->noalloc_stage.data();
+  ChanTable ch{};
+  fill_chan(c, obs, ch);
+  std::memcpy(h + kNoAllocChanOff, &ch, sizeof ch);
+  SrcModel *hs = reinterpret_cast<SrcModel *>(h + kNoAllocSrcOff);
+  SrcMixed *hs32 = reinterpret_cast<SrcMixed *>(h + kNoAllocSrc32Off);
+  for (int64_t s = 0; s < n; ++s) {
+    hs[s] = pack_source(c->p, cat, src_begin + s);
+    hs32[s] = to_mixed(hs[s]);
+  }
+  HIPCHK(c, hipMemcpyAsync(ptr + kNoAllocChanOff, h + kNoAllocChanOff, sizeof(ChanTable), hipMemcpyHostToDevice,
+                           c->stream));
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(ptr + kNoAllocSrcOff, hs, sizeof(SrcModel) * (size_t)n, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(ptr + kNoAllocSrc32Off, hs32, sizeof(SrcMixed) * (size_t)n, hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  ModelArgs a{};
+  a.u_m = obs->u_m;
+  a.v_m = obs->v_m;
+  a.w_m = obs->w_m;
+  a.n_rows = obs->n_rows;
+  a.n_chan = obs->n_chan;
+  a.mode = mode;
+  a.chan = reinterpret_cast<const ChanTable *>(ptr + kNoAllocChanOff);
+  a.src = reinterpret_cast<const SrcModel *>(ptr + kNoAllocSrcOff);
+  a.src32 = reinterpret_cast<const SrcMixed *>(ptr + kNoAllocSrc32Off);
+  a.s_begin = 0;
+  a.s_end = (int32_t)n;
   a.vis_in = obs->vis;
   a.out = out;
   hipError_t e = launch_model(a, c->p.precision == RLF_MIXED, c->stream);

@@ -44,6 +44,8 @@ struct rlf_ctx {
   // pinned staging ring of the asynchronous table uploads
   char *pinned = nullptr;
   size_t pinned_off = 0;
+  // host staging of rlf_model_vis_noalloc's tables (sized at creation)
+  std::vector<unsigned char> noalloc_stage;
 };
 
 struct rlf_facets {

@@ -69,6 +69,8 @@ _SIGNATURES = {
     "rlf_alpha_from_flux": ([_c_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _c_dp], ctypes.c_int),
     "rlf_model_vis": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), ctypes.c_int64,
                        ctypes.c_int64, _c_vp, ctypes.c_int], ctypes.c_int),
+    "rlf_model_vis_noalloc": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), ctypes.c_int64,
+                               ctypes.c_int64, _c_vp, ctypes.c_int], ctypes.c_int),
     "rlf_facets_create": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), ctypes.POINTER(_c_vp)],
                           ctypes.c_int),
     "rlf_extract_facets": ([_c_vp, ctypes.POINTER(rlf_obs), ctypes.POINTER(rlf_catalog), _c_vp, _c_vp],
@@ -224,6 +226,14 @@ class Context:
         end = c.n_src if src_end is None else src_end
         return self._check(lib().rlf_model_vis(self.h, ctypes.byref(o), ctypes.byref(c), int(src_begin), int(end),
                                                _ptr(out), int(mode)))
+
+    def model_vis_noalloc(self, obs: Obs, cat, out, mode=RLF_MODEL_WRITE, src_begin=0, src_end=None):
+        """rlf_model_vis_noalloc: model_vis without device allocation (at most 4096 sources per call)."""
+        o = obs.c()
+        c, keep = catalog(cat)
+        end = c.n_src if src_end is None else src_end
+        return self._check(lib().rlf_model_vis_noalloc(self.h, ctypes.byref(o), ctypes.byref(c), int(src_begin),
+                                                       int(end), _ptr(out), int(mode)))
 
     def facets_create(self, obs: Obs, cat, prior_mu=None) -> "Facets":
         o = obs.c()

@@ -55,53 +55,147 @@ MODEL_FLOP_PAIR = 19
 #   sky model (k_model): fetch 372.9 / 298.3 MB, write 148.3 / 74.1 MB
 TRAFFIC_BYTES = {"fp64": {"extract": 2830.3e6, "fit": 356.6e6, "model": 521.2e6},
                  "mixed": {"extract": 2175.7e6, "fit": 280.5e6, "model": 372.4e6}}
-# VALU lane-slot roofline: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
-# Slots per unit of work are the VALU instructions of the compiled hot loop
-# at their measured gfx950 cost (FP64 and FP32 add/mul/FMA/round and FP32
-# v_sin/v_cos/v_rsq 1, v_rsq FP64 4):
-#   extraction FP64 41 = phase 3, reduction 3, sincos polynomials + table
-#     index + rotation 12, profile (quadratic form 3 with the flux folded
-#     into it, rsq 4, correction 4) 11, cell index 4, run key + compare 2,
-#     run sums 6;  mixed 30 (phase and fractional part in FP64, v_sin/v_cos,
-#     FP32 rotation and profile, widening, FP64 run sums)
-#   likelihood per (cell, point, knot): FP64 12 = x 1, rsq 4 + correction 4,
-#     D 1, Mm 2;  mixed 7 = x 1, rsq 1, cube 2, D 1, Mm 2; plus 5 per
-#     (cell, point) shared by the knots (mixed 10: two knot passes)
-#   sky-model DFT FP64 32 = phase 3, reduction + sincos 15, profile 3 + 8,
-#     amplitude 1, accumulate 2;  mixed 16 = phase 3, fractional part and
-#     conversion 2, sin + cos 2, profile 3 + rsq 1 + cube 2, amplitude 1,
-#     accumulate 2
+# VALU roofline in lane-slots: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s,
+# with the method's necessary work per unit priced as in the hot-path scope's
+# cost model (FP64 FMA and FP32 add/mul/FMA 1 slot, transcendentals 4):
+#   sky-model DFT, per (visibility, source): phase 5, cvt 1, sin + cos +
+#     rsqrt 12, shape form 6, x 1, r^3 S 3, accumulate 2               = 30
+#   extraction, per (visibility, source): phase 6, cell index 6, sincos +
+#     rsqrt 12, complex rotation 4, own model 9, weight + accumulate 5 = 42
+#   likelihood, per (cell, e point, knot): x 1, rsqrt 4, r^3 2, D and M 3,
+#     the quadratic form 6 per (cell, e point) over the 20 knots 0.3   = 10.3
+#     (+1 for the blocked FP32 sums of the mixed form)                 = 11.3
 SLOT_PEAK = 256 * 64 * 2.4e9
-SLOTS = {"fp64": {"extract": 41, "fit_knot": 12, "fit_point": 5, "model": 32},
-         "mixed": {"extract": 30, "fit_knot": 7, "fit_point": 10, "model": 16}}
+SLOTS = {"fp64": {"extract": 42.0, "fit": 10.3, "model": 30.0},
+         "mixed": {"extract": 42.0, "fit": 11.3, "model": 30.0}}
+# VALU wave-instructions per launch at this workload (SQ_INSTS_VALU, rocprofv3,
+# profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md), for the issue rate, and
+# the VALU probe (probe/valu_probe.hip) whose instruction stream bounds each
+# kernel's: FP64 kernels by the FP64 FMA stream (the likelihood, one
+# v_rsq_f64 in ten instructions, by the stream with one in eight), the mixed
+# ones by FP32 FMA streams with one FP32 transcendental in six or four
+# (transcendentals co-issue, so such a stream issues above one instruction
+# per CU per cycle)
+VALU_INSTR = {"fp64": {"extract": 5.969e9, "fit": 5.781e9, "model": 4.236e9},
+              "mixed": {"extract": 4.745e9, "fit": 4.853e9, "model": 2.321e9}}
+CEILING_PROBE = {"fp64": {"extract": "fma_f64", "fit": "rsq_f64+2cvt+add+4fma_f64", "model": "fma_f64"},
+                 "mixed": {"extract": "rsq_f32+add+4fma_f32", "fit": "rsq_f32+add+4fma_f32",
+                           "model": "rsq_f32+add+2fma_f32"}}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(o, vis_true_fn, cat, n_sample, p):
-    """Oracle timed on a bounded sample: for each sampled source, its share of
-    the sky model (its visibilities at every row), its extraction and its
-    fit -- the per-source work of one step."""
+_CPU = {}
+
+
+def _cpu_source(s):
+    """One sampled source's share of a step on the oracle, stage by stage:
+    its sky-model term at every visibility, its extraction, its fit."""
     import oracle
-    idx = np.linspace(0, cat.n_src - 1, n_sample).round().astype(int)
-    rng = np.random.default_rng(0)
-    nz = 1e-3 * (rng.standard_normal(o.n_rows) + 1j * rng.standard_normal(o.n_rows))
+    o, cat, p, nz = _CPU["o"], _CPU["cat"], _CPU["p"], _CPU["nz"]
     t0 = time.perf_counter()
-    for s in idx:
-        sky_s = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat, p.ref_freq_hz, p.beta, sources=[int(s)])
-        resid = nz - sky_s
-        src = (cat.l[s], cat.m[s], cat.flux_jy[s], cat.alpha_arcsec[s], cat.e1[s], cat.e2[s])
-        f = oracle.extract_facet(o.u_m, o.v_m, o.w_m, o.freq_hz, o.weight, resid, src,
-                                 oracle.facet_theta(cat.alpha_arcsec[s], p.K), p.ref_freq_hz, p.beta)
-        oracle.fit_source(f, cat.flux_jy[s], p)
-    dt = time.perf_counter() - t0
-    return dict(value=round(n_sample / dt, 4), unit="sources/s", cores=1, kind="oracle",
-                sample=f"{n_sample} of {cat.n_src} sources: per source its sky-model term at all "
-                       f"{o.n_rows} visibilities, its extraction and its full-grid fit "
-                       f"(NumPy FP64, single thread), {dt:.1f} s",
-                host_cores_available=len(os.sched_getaffinity(0)))
+    sky_s = oracle.sky_model(o.u_m, o.v_m, o.w_m, o.freq_hz, cat, p.ref_freq_hz, p.beta, sources=[s])
+    t1 = time.perf_counter()
+    src = (cat.l[s], cat.m[s], cat.flux_jy[s], cat.alpha_arcsec[s], cat.e1[s], cat.e2[s])
+    f = oracle.extract_facet(o.u_m, o.v_m, o.w_m, o.freq_hz, o.weight, nz - sky_s, src,
+                             oracle.facet_theta(cat.alpha_arcsec[s], p.K), p.ref_freq_hz, p.beta)
+    t2 = time.perf_counter()
+    oracle.fit_source(f, cat.flux_jy[s], p)
+    t3 = time.perf_counter()
+    return t1 - t0, t2 - t1, t3 - t2
+
+
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_sample):
+    """The oracle timed on the host's cores (one process per core, at most 16)
+    on a bounded sample of the benchmark's step: for each sampled source, its
+    sky-model term over all visibilities, its extraction and its fit.  Runs
+    before the process touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
+
+    import oracle
+    from paper_2203_14071_amd import synth
+    cfg = synth.CONFIGS[1]
+    o = synth.observation(1)
+    cat = synth.catalogue(cfg, synth.rng(1, synth.STREAM_CAT))
+    cat = cat.with_shape(np.zeros(cat.n_src), np.zeros(cat.n_src))
+    rng = np.random.default_rng(0)
+    nz = cfg.noise_sigma_jy * (rng.standard_normal(o.n_rows) + 1j * rng.standard_normal(o.n_rows))
+    cores = min(16, len(os.sched_getaffinity(0)))
+    idx = np.linspace(0, cat.n_src - 1, n_sample).round().astype(int)
+    _CPU.update(o=o, cat=cat, p=oracle.Params(), nz=nz)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        times = np.array(pool.map(_cpu_source, idx.tolist(), chunksize=1))
+    wall = time.perf_counter() - t0
+    _CPU.clear()
+    per = times.mean(axis=0)
+    return dict(value=round(n_sample / wall, 4), unit="sources/s", cores=cores, kind="oracle",
+                sample=f"{n_sample} of {cat.n_src} sources of the benchmark's field, evenly spaced in catalogue "
+                       f"order: per source its sky-model term at all {o.n_rows} visibilities, its extraction and "
+                       f"its full-grid fit (NumPy FP64 oracle, one process per core), {wall:.1f} s wall",
+                cpu_model=_cpu_model(), host_cores_available=len(os.sched_getaffinity(0)),
+                stage_core_s_per_source={"sky_model_term": round(float(per[0]), 4),
+                                         "extraction": round(float(per[1]), 4), "fit": round(float(per[2]), 4)},
+                full_field_s_at_these_cores=round(float(per.sum()) * cat.n_src / cores, 1))
+
+
+# VALU probe kernels (probe/valu_probe.hip): name, VALU instructions per lane
+# per loop iteration by type (counted in the compiled loop bodies).
+PROBES = [
+    ("fma_f64", {"fma64": 8}), ("fma_f32", {"fma32": 8}), ("rsq_f64", {"rsq64": 8}),
+    ("rsq_f32", {"rsq32": 8}), ("sin_f32", {"sin32": 8}), ("exp_f32+add", {"exp32": 8, "add32": 8}),
+    ("rsq_f32+add+fma_f32", {"rsq32": 8, "add32": 8, "fma32": 8}),
+    ("rsq_f32+add+2fma_f32", {"rsq32": 8, "add32": 8, "fma32": 16}),
+    ("rsq_f32+add+4fma_f32", {"rsq32": 8, "add32": 8, "fma32": 32}),
+    ("sin_f32+2fma_f32", {"sin32": 8, "fma32": 16}),
+    ("rsq_f64+2cvt+add+2fma_f64", {"rsq64": 8, "cvt": 16, "add64": 8, "fma64": 16}),
+    ("rsq_f64+2cvt+add+4fma_f64", {"rsq64": 8, "cvt": 16, "add64": 8, "fma64": 32}),
+    ("cvt_f32_f64+cvt_f64_f32+add_f64", {"cvt": 16, "add64": 8}),
+]
+CLOCK_HZ, N_CU = 2.4e9, 256
+
+
+def valu_probe(iters=8192, blocks=2048):
+    """Issue rate of each probe kernel: VALU wave-instructions per CU per
+    cycle at the 2.4 GHz peak clock (1.0 = one per cycle per CU, i.e. every
+    SIMD issuing a 64-lane instruction every four cycles)."""
+    import ctypes
+    from paper_2203_14071_amd import build
+    if not os.path.exists(build.PROBE_LIB):
+        raise RuntimeError(f"{build.PROBE_LIB} is missing: build first")
+    L = ctypes.CDLL(build.PROBE_LIB)
+    L.valu_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    assert L.valu_probe_count() == len(PROBES)
+    waves = blocks * 4
+    rows = []
+    for op, (name, mix) in enumerate(PROBES):
+        ms, hz = ctypes.c_double(), ctypes.c_double()
+        rc = L.valu_probe_run(op, blocks, iters, 5, ctypes.byref(ms), ctypes.byref(hz))
+        if rc != 0:
+            raise RuntimeError(f"valu probe {name}: HIP error {rc}")
+        per_iter = sum(mix.values())
+        instr = float(waves) * iters * per_iter
+        rate = instr / (ms.value * 1e-3) / (CLOCK_HZ * N_CU)
+        at_clock = instr / (ms.value * 1e-3) / (hz.value * N_CU) if hz.value > 0 else None
+        rows.append({"probe": name, "instr_per_iter": mix, "ms": round(ms.value, 4),
+                     "wave_instr_per_cu_cycle": round(rate, 4), "shader_clock_hz": round(hz.value, -6),
+                     "wave_instr_per_cu_cycle_at_measured_clock": None if at_clock is None else round(at_clock, 4)})
+        log(f"[valu] {name}: {ms.value:.3f} ms, {rate:.3f} wave-instr / CU / cycle at 2.4 GHz; "
+            f"clock {hz.value / 1e9:.3f} GHz")
+    return {"clock_hz": CLOCK_HZ, "cus": N_CU, "blocks": blocks, "threads": 256, "iters": iters, "probes": rows}
 
 
 def _values(text, typ):
@@ -115,7 +209,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="sources in the oracle baseline sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=160,
+                    help="sources in the oracle baseline sample, timed on the host cores (0 = skip)")
     ap.add_argument("--only", action="store_true", help="time only the --precision form (for profiling)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the config-3 batched / surrogate block")
     ap.add_argument("--only-config3", action="store_true",
@@ -138,9 +233,14 @@ def main():
                     help="lattice strides of the lattice-seeded window fit to compare ('' or none = skip)")
     ap.add_argument("--full-frac", type=float, default=0.25,
                     help="windows above this fraction of the grid are fitted on the whole grid")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the VALU issue-rate probe (roofline ceilings) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.valu_probe:
+        print(json.dumps(valu_probe()), flush=True)
+        return
     if args.copy_calibration:
         import torch
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -155,8 +255,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    # the oracle on the host's cores first, before this process initialises the GPU
+    cpu = None
+    if args.cpu_sample > 0 and not args.only and not args.only_config3:
+        log(f"[bench] timing the oracle on {args.cpu_sample} sources")
+        cpu = cpu_baseline(args.cpu_sample)
+        log(f"[bench] oracle: {cpu['value']} sources/s on {cpu['cores']} cores ({cpu['cpu_model']})")
 
+    import torch
 
     pops = [] if args.populations in ("", "none") else args.populations.split(",")
     if args.only_config3:
@@ -174,17 +280,19 @@ def main():
         return
     other = "mixed" if args.precision == "fp64" else "fp64"
     other_form = run_form(other, args.steps, args.warmup, lattice_strides=lattice_strides)
-    de = np.max(np.abs(np.concatenate([main_form["e1"] - other_form["e1"], main_form["e2"] - other_form["e2"]])))
+    dev_e = np.maximum(np.abs(main_form["e1"] - other_form["e1"]), np.abs(main_form["e2"] - other_form["e2"]))
+    de = np.max(dev_e)
     res["precision_form"] = {
         "precision": other, "value": other_form["json"]["value"], "unit": "sources/s",
         "ms_per_step": other_form["json"]["ms_per_step"], "stage_ms": other_form["json"]["stage_ms"],
         "gvis_per_s_extract": other_form["json"]["gvis_per_s_extract"],
         "roofline": other_form["json"]["roofline"],
         "kernel_rooflines": other_form["json"]["kernel_rooflines"],
-        "slot_roofline_frac": other_form["json"]["slot_roofline_frac"],
         "lattice_seeded_fit": other_form["json"]["lattice_seeded_fit"],
         "max_abs_de_vs_" + args.precision: float(de),
-        "note": "same synthetic field; the mixed form takes complex64 visibilities and f32 weights",
+        "sources_with_abs_de_above_1e-4": int(np.count_nonzero(dev_e > 1e-4)),
+        "note": "same synthetic field (simulated in FP64); the mixed form takes it rounded to complex64 "
+                "visibilities and f32 weights",
     }
     if not args.no_surrogate:
         res["batched_and_surrogate"] = run_surrogate(max(3, args.steps // 3), args.train_sources, args.epochs,
@@ -200,11 +308,23 @@ def main():
                     "e_measured - e_true = m e_true + c over good fits (Sec. 4.2)",
             "paper_context": "K = 38: m1 = 0.0366 +- 0.0028, m2 = 0.0731 +- 0.0026, 0.3 % bad (their data and fit)",
             "rows": rows, "s": round(time.perf_counter() - t0, 2)}
-    if args.cpu_sample > 0:
-        log(f"[bench] timing the oracle on {args.cpu_sample} sources")
-        import oracle  # the CPU-baseline leg only
-        res["cpu_baseline"] = cpu_baseline(main_form["obs_host"], None, main_form["cat"], args.cpu_sample,
-                                           oracle.Params())
+    # the VALU issue ceilings of the kernels' instruction streams, measured here
+    try:
+        probe = valu_probe()
+        res["valu_ceilings"] = probe
+        rates = {r["probe"]: r["wave_instr_per_cu_cycle"] for r in probe["probes"]}
+        blocks = [res["kernel_rooflines"], res.get("precision_form", {}).get("kernel_rooflines", {}),
+                  {"_": res["roofline"]}, {"_": res.get("precision_form", {}).get("roofline", {})}]
+        for blk in blocks:
+            for kr in blk.values():
+                iss = kr.get("issue")
+                if iss and iss["ceiling_probe"] in rates:
+                    iss["ceiling"] = rates[iss["ceiling_probe"]]
+                    iss["frac_of_ceiling"] = round(iss["wave_instr_per_cu_cycle"] / iss["ceiling"], 4)
+    except (OSError, RuntimeError) as e:
+        log(f"[bench] VALU probe not run: {e}")
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 
@@ -475,15 +595,24 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
     dev = "cuda:0"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    cdt = torch.complex64 if mixed else torch.complex128
-    wdt = torch.float32 if mixed else torch.float64
     t = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
-    vis = t(nz, cdt)
-    obs = rlf.Obs(t(o.u_m), t(o.v_m), t(o.w_m), o.freq_hz, vis, t(o.weight, wdt))
+    # synthetic data, the same for both forms: the true-shape sky (this
+    # library's FP64 model) added onto the noise in FP64; the mixed form gets
+    # it rounded to complex64, with float32 weights
+    vis = t(nz, torch.complex128)
+    w64 = t(o.weight)
+    obs = rlf.Obs(t(o.u_m), t(o.v_m), t(o.w_m), o.freq_hz, vis, w64)
+    sim = rlf.Context(0, stream.cuda_stream, rlf.params(precision=rlf.RLF_FP64))
+    sim.model_vis(obs, cat, vis, mode=rlf.RLF_MODEL_ACCUMULATE)
+    sim.sync()
+    sim.close()
+    if mixed:
+        vis = vis.to(torch.complex64)
+        obs = rlf.Obs(obs.u_m, obs.v_m, obs.w_m, o.freq_hz, vis, w64.to(torch.float32))
+        del w64
+        torch.cuda.empty_cache()
     p = rlf.params(precision=rlf.RLF_MIXED if mixed else rlf.RLF_FP64)
     ctx = rlf.Context(0, stream.cuda_stream, p)
-    # synthetic data: true-shape sky (this library's model) added onto the noise
-    ctx.model_vis(obs, cat, vis, mode=rlf.RLF_MODEL_ACCUMULATE)
     facets = ctx.facets_create(obs, catc)
     resid = torch.empty_like(vis)
     n = cat.n_src
@@ -609,35 +738,38 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
     peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
     pairs = float(n_vis) * n
 
-    def roof(name, flop, ms, note):
-        a = flop / (ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": round(a, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(a / peak, 4), "algorithmic_flop": flop, "note": note}
-
-    kernels = {
-        "extract": roof("facet extraction (k_extract; the stage also runs the sorted-order gather and compaction, "
-                        "<2 % of it)", EXTRACT_FLOP_PAIR * pairs, stage_ms[1],
-                        f"{EXTRACT_FLOP_PAIR} FLOP per (visibility, source) pair x {pairs:.4g} pairs"),
-        "fit": roof("likelihood grid (k_fit) + estimator",
-                    float(np.sum(cells)) * n_valid * (FIT_FLOP_CELL_POINT + FIT_FLOP_CELL_POINT_KNOT * p.num_r),
-                    stage_ms[2], f"{FIT_FLOP_CELL_POINT} FLOP per (cell, e point) + {FIT_FLOP_CELL_POINT_KNOT} per "
-                                 f"(cell, e point, knot) x {int(np.sum(cells))} cells x {n_valid} x {p.num_r}"),
-        "model": roof("sky-model residual DFT (k_model)", MODEL_FLOP_PAIR * pairs, stage_ms[0],
-                      f"{MODEL_FLOP_PAIR} FLOP per (visibility, source) pair x {pairs:.4g} pairs"),
-    }
-    sl = SLOTS[precision]
-    fit_units = float(np.sum(cells)) * n_valid
-    slot_roofline = {
-        "peak_lane_slots_per_s": SLOT_PEAK,
-        "extract": round(sl["extract"] * pairs / (stage_ms[1] * 1e-3) / SLOT_PEAK, 4),
-        "fit": round((sl["fit_knot"] * p.num_r + sl["fit_point"]) * fit_units / (stage_ms[2] * 1e-3) / SLOT_PEAK, 4),
-        "model": round(sl["model"] * pairs / (stage_ms[0] * 1e-3) / SLOT_PEAK, 4),
-        "slots_per_unit": sl,
-    }
-    dominant = max(("extract", "fit", "model"), key=lambda k: {"model": stage_ms[0], "extract": stage_ms[1],
-                                                               "fit": stage_ms[2]}[k])
-    for k in kernels:
-        kernels[k]["traffic"] = TRAFFIC_BYTES[precision][k]
+    fit_units = float(np.sum(cells)) * n_valid * p.num_r
+    units = {"extract": pairs, "fit": fit_units, "model": pairs}
+    stage_idx = {"model": 0, "extract": 1, "fit": 2}
+    names = {"extract": "facet extraction (k_extract; the stage also runs the sorted-order gather and the "
+                        "compaction, < 2 % of it)",
+             "fit": "likelihood grid (k_fit) + estimator (k_estimate, 0.05 ms)",
+             "model": "sky-model residual DFT (k_model)"}
+    unit_names = {"extract": "(visibility, source) pair", "fit": "(cell, e point, knot)",
+                  "model": "(visibility, source) pair"}
+    flop = {"extract": EXTRACT_FLOP_PAIR * pairs,
+            "fit": float(np.sum(cells)) * n_valid * (FIT_FLOP_CELL_POINT + FIT_FLOP_CELL_POINT_KNOT * p.num_r),
+            "model": MODEL_FLOP_PAIR * pairs}
+    peak_flop = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    kernels = {}
+    for k in ("extract", "fit", "model"):
+        ms = float(stage_ms[stage_idx[k]])
+        slots = SLOTS[precision][k] * units[k]
+        ach = slots / (ms * 1e-3) / 1e12
+        fl = flop[k] / (ms * 1e-3) / 1e12
+        kernels[k] = {
+            "kernel": names[k], "bound": "alu", "achieved": round(ach, 3), "peak": round(SLOT_PEAK / 1e12, 3),
+            "unit": "T VALU lane-slots/s", "frac": round(ach * 1e12 / SLOT_PEAK, 4),
+            "traffic": TRAFFIC_BYTES[precision][k],
+            "basis": f"{SLOTS[precision][k]} lane-slots per {unit_names[k]} x {units[k]:.6g} units / "
+                     f"{ms:.3f} ms; peak 256 CUs x 64 lanes x 2.4 GHz",
+            "flop_basis": {"achieved": round(fl, 3), "peak": peak_flop, "unit": "TFLOP/s",
+                           "frac": round(fl / peak_flop, 4), "algorithmic_flop": flop[k]},
+            "issue": {"valu_wave_instr": VALU_INSTR[precision][k],
+                      "wave_instr_per_cu_cycle": round(VALU_INSTR[precision][k] / (ms * 1e-3) / (CLOCK_HZ * N_CU), 4),
+                      "ceiling_probe": CEILING_PROBE[precision][k]},
+        }
+    dominant = max(("extract", "fit", "model"), key=lambda k: stage_ms[stage_idx[k]])
     roofline = dict(kernels[dominant])
     flags = out["flags"].cpu().numpy()
     e1 = out["e1"].cpu().numpy()
@@ -670,7 +802,6 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
                      "fit": round(stage_ms[2], 4)},
         "roofline": roofline,
         "kernel_rooflines": kernels,
-        "slot_roofline_frac": slot_roofline,
         "facet_cells": {"total": int(cells.sum()), "mean": round(float(cells.mean()), 1),
                         "min": int(cells.min()), "max": int(cells.max())},
         "fit_quality": {"rms_e_minus_true": round(rms, 5), "bad_var": int(np.sum(flags & 1)),

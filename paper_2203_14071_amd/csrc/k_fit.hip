@@ -82,10 +82,13 @@ __device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int
 #pragma unroll
     for (int k = 0; k < KP; ++k) D[k] = M[k] = 0.0;
     if (!kMixed) {
-      const double a11 = 1.0 + e1, a12 = e2, a22 = 1.0 - e1;
+      // A^{-T} with its 1/det folded in, so that the knot scales s_k stay
+      // wave-uniform (SGPR operands: 40 VGPRs fewer than per-lane s_k g)
+      const double id = 1.0 / det;
+      const double a11 = (1.0 + e1) * id, a12 = e2 * id, a22 = (1.0 - e1) * id;
       double sk[KP];
 #pragma unroll
-      for (int k = 0; k < KP; ++k) sk[k] = k0 + k < num_r ? a.sk[k0 + k] * g : 0.0;
+      for (int k = 0; k < KP; ++k) sk[k] = k0 + k < num_r ? a.sk[k0 + k] : 0.0;
       cell_sums_f64<KP>(a.fit64, c0, c1, a11, a12, a22, sk, num_r - k0, D, M);
     } else {
       const float a11 = (float)(1.0 + e1), a12 = (float)e2, a22 = (float)(1.0 - e1);

@@ -216,8 +216,8 @@ def main():
     ap.add_argument("--only-config3", action="store_true",
                     help="run only the config-3 block (with --populations none: no network, for profiling)")
     ap.add_argument("--train-sources", type=int, default=200_000)
-    ap.add_argument("--epochs", type=int, default=24)
-    ap.add_argument("--nsigma", default="3,4", help="window half-widths (in predicted sigmas) to compare")
+    ap.add_argument("--epochs", type=int, default=96)
+    ap.add_argument("--nsigma", default="2.5,3", help="window half-widths (in predicted sigmas) to compare")
     ap.add_argument("--populations", default="config1,config3",
                     help="training source populations to compare (config-1 generator either way)")
     ap.add_argument("--check-stride", type=int, default=4)
@@ -231,7 +231,7 @@ def main():
     ap.add_argument("--pos-sides", default="3,5,7", help="offset grids (per axis) to compare with the fixed position")
     ap.add_argument("--lattice-strides", default="4,3",
                     help="lattice strides of the lattice-seeded window fit to compare ('' or none = skip)")
-    ap.add_argument("--full-frac", type=float, default=0.25,
+    ap.add_argument("--full-frac", type=float, default=0.6,
                     help="windows above this fraction of the grid are fitted on the whole grid")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only run the VALU issue-rate probe (roofline ceilings) and print its JSON")
@@ -360,6 +360,8 @@ def _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, fu
         evals = _evaluated_points(w, check_stride) + np.count_nonzero(refit) * 6333
         y = win.y.cpu().numpy()
         pred_rms = float(np.sqrt(np.mean((y[:, 0] - cat.e1) ** 2 + (y[:, 1] - cat.e2) ** 2) / 2))
+        fin = np.isfinite(a["e1"])
+        pred_rms_full = float(np.sqrt(np.mean((y[fin, 0] - a["e1"][fin]) ** 2 + (y[fin, 1] - a["e2"][fin]) ** 2) / 2))
         rms = float(np.sqrt(np.mean(de ** 2)))
         fb = float(np.mean(refit))
         log(f"[bench] {label}, nsigma {ns}: narrowed fit {t_nar:.2f} ms (full {t_full:.2f} ms); RMS(de) {rms:.2e}; "
@@ -375,7 +377,8 @@ def _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, fu
                     "mean_window_points": round(float(area.mean()), 1),
                     "full_grid_windows": int(np.count_nonzero(area == 81 * 81)),
                     "grid_points_evaluated_vs_full": round(evals / (6333 * n), 4),
-                    "network_rms_e_vs_true": round(pred_rms, 4)})
+                    "network_rms_e_vs_true": round(pred_rms, 4),
+                    "network_rms_e_vs_full_grid_estimate": round(pred_rms_full, 4)})
         rows.append(row)
     del win
     return rows
@@ -528,12 +531,12 @@ def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, fu
         net = rlf.Mlp(ctx, 512)
         net.set_state(surrogate.init_params())
         t0 = time.perf_counter()
-        x, tg = surrogate.training_set(ctx, net, n_train, 20_000, log=log, population=pop)
+        ts = surrogate.training_set(ctx, net, n_train, 20_000, log=log, population=pop)
         t_sim = time.perf_counter() - t0
         t0 = time.perf_counter()
-        hist = surrogate.train(ctx, net, x, tg, epochs, log=log)
+        hist = surrogate.train(ctx, net, ts, epochs, log=log)
         t_train = time.perf_counter() - t0
-        del x, tg
+        del ts
         torch.cuda.empty_cache()
         training.append({"population": pop, "sources": n_train, "epochs": epochs, "simulate_s": round(t_sim, 2),
                          "train_s": round(t_train, 2), "loss_per_epoch": [round(h, 4) for h in hist]})

@@ -444,6 +444,22 @@ int rlf_mlp_forward(rlf_mlp *net, const void *x, int64_t rows, float *y);
  * batch loss is written to device *loss (FP64). */
 int rlf_mlp_train_step(rlf_mlp *net, const void *x, const float *target, int64_t rows, float lr, double *loss);
 
+/* Training targets around the method's own fits (the network then learns the
+ * posterior mean as its mean and, through the NLL, the posterior width plus
+ * its own error as its variance): for each of `rows` sources, from its
+ * full-grid estimate (e1, e2) and spread (s1, s2) (device FP64 [rows], as
+ * rlf_fit_sources writes them) and ln alpha (device FP32 [rows]),
+ * target = (e1 + kappa s1 z_{2i}, e2 + kappa s2 z_{2i+1}, ln alpha), device
+ * FP32 [rows x 3].  z_j is the j-th standard normal number of stream `seed`:
+ * the Box-Muller transform, in FP64, of uniforms from the SplitMix64
+ * generator used counter-wise (value k of stream seed is the SplitMix64
+ * output mix of seed + k * 0x9E3779B97F4A7C15; u1 = ((h(2j+1) >> 11) + 1)
+ * 2^-53, u2 = (h(2j+2) >> 11) 2^-53, z_j = sqrt(-2 ln u1) cos(2 pi u2)).
+ * A row whose estimate or spread is not finite gets (0, 0, ln alpha).
+ * kappa >= 0 scales the spread. */
+int rlf_mlp_posterior_targets(rlf_ctx *ctx, const double *e1, const double *e2, const double *s1, const double *s2,
+                              const float *ln_alpha, int64_t rows, double kappa, uint64_t seed, float *target);
+
 /* Window boxes for rlf_fit_sources mode 1 from predictions y (device FP32
  * [rows x 6]): per axis, mu +- nsigma exp(s'/2) (s' the floored
  * log-variance), widened to at least +- min_half grid steps around the

@@ -257,6 +257,41 @@ __global__ __launch_bounds__(256) void k_windows(const float *y, int64_t n, doub
   }
 }
 
+// SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the output mix of state seed + k * golden gamma,
+// used here as a counter-based generator (value k of stream `seed`).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Standard normal number j of stream `seed` by the Box-Muller transform of
+// the uniforms u1 = (h(2j+1) >> 11 + 1) 2^-53 in (0, 1] and
+// u2 = (h(2j+2) >> 11) 2^-53 in [0, 1), h the counter generator above:
+// sqrt(-2 ln u1) cos(2 pi u2), in FP64.
+__device__ __forceinline__ double std_normal(uint64_t seed, uint64_t j) {
+  const double u1 = ((double)(splitmix64(seed, 2 * j + 1) >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(splitmix64(seed, 2 * j + 2) >> 11) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+// Training targets drawn around the method's own estimates: row i gets
+// (e1_i + kappa s1_i z_{2i}, e2_i + kappa s2_i z_{2i+1}, ln alpha_i) with z
+// the normal numbers of stream `seed`; a row whose estimate or spread is not
+// finite gets (0, 0, ln alpha_i).
+__global__ __launch_bounds__(256) void k_posterior_targets(const double *e1, const double *e2, const double *s1,
+                                                           const double *s2, const float *ln_alpha, int64_t n,
+                                                           double kappa, uint64_t seed, float *t) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool ok = isfinite(e1[i]) && isfinite(e2[i]) && isfinite(s1[i]) && isfinite(s2[i]);
+    t[i * 3 + 0] = ok ? (float)(e1[i] + kappa * s1[i] * std_normal(seed, 2 * (uint64_t)i)) : 0.0f;
+    t[i * 3 + 1] = ok ? (float)(e2[i] + kappa * s2[i] * std_normal(seed, 2 * (uint64_t)i + 1)) : 0.0f;
+    t[i * 3 + 2] = ln_alpha[i];
+  }
+}
+
 unsigned grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
@@ -311,6 +346,14 @@ hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st) 
 
 hipError_t launch_features(const FeatureArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_features, dim3(a.n_src), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_posterior_targets(const double *e1, const double *e2, const double *s1, const double *s2,
+                                   const float *ln_alpha, int64_t n, double kappa, uint64_t seed, float *t,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(k_posterior_targets, dim3(grid_for(n)), dim3(256), 0, st, e1, e2, s1, s2, ln_alpha, n, kappa,
+                     seed, t);
   return hipGetLastError();
 }
 

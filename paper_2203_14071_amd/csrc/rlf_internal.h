@@ -322,6 +322,9 @@ hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v,
                        hipStream_t st);
 hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);
 hipError_t launch_features(const FeatureArgs &a, hipStream_t st);
+hipError_t launch_posterior_targets(const double *e1, const double *e2, const double *s1, const double *s2,
+                                   const float *ln_alpha, int64_t n, double kappa, uint64_t seed, float *t,
+                                   hipStream_t st);
 hipError_t launch_windows(const float *y, int64_t n, double nsigma, int n_e, double step, int min_half,
                           double full_frac, int32_t *win, hipStream_t st);
 

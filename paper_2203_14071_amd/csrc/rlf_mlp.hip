@@ -367,6 +367,16 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   return RLF_OK;
 }
 
+int rlf_mlp_posterior_targets(rlf_ctx *c, const double *e1, const double *e2, const double *s1, const double *s2,
+                              const float *ln_alpha, int64_t rows, double kappa, uint64_t seed, float *target) {
+  if (!c) return RLF_EINVAL;
+  if (!e1 || !e2 || !s1 || !s2 || !ln_alpha || !target || rows < 1 || !(kappa >= 0.0) || !std::isfinite(kappa))
+    return fail(c, RLF_EINVAL, "rlf_mlp_posterior_targets: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_posterior_targets(e1, e2, s1, s2, ln_alpha, rows, kappa, seed, target, c->stream));
+  return RLF_OK;
+}
+
 int rlf_mlp_windows(rlf_ctx *c, const float *y, int64_t rows, double nsigma, int32_t min_half, double full_frac,
                     int32_t *window) {
   if (!c) return RLF_EINVAL;

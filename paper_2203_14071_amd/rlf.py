@@ -99,6 +99,8 @@ _SIGNATURES = {
     "rlf_mlp_features": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
     "rlf_mlp_forward": ([_c_vp, _c_vp, ctypes.c_int64, _c_vp], ctypes.c_int),
     "rlf_mlp_train_step": ([_c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_float, _c_vp], ctypes.c_int),
+    "rlf_mlp_posterior_targets": ([_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_uint64, _c_vp], ctypes.c_int),
     "rlf_mlp_windows": ([_c_vp, _c_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _c_vp],
                         ctypes.c_int),
 }
@@ -435,6 +437,12 @@ class Mlp:
     def train_step(self, x, target, lr, loss):
         return self.ctx._check(lib().rlf_mlp_train_step(self.h, _ptr(x), _ptr(target), int(x.shape[0]),
                                                         float(lr), _ptr(loss)))
+
+    def posterior_targets(self, e1, e2, s1, s2, ln_alpha, target, kappa, seed):
+        """rlf_mlp_posterior_targets: targets drawn around the full-grid estimates."""
+        return self.ctx._check(lib().rlf_mlp_posterior_targets(self.ctx.h, _ptr(e1), _ptr(e2), _ptr(s1), _ptr(s2),
+                                                               _ptr(ln_alpha), int(e1.shape[0]), float(kappa),
+                                                               int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(target)))
 
     def windows(self, y, window, nsigma=3.0, min_half=3, full_frac=1.0):
         return self.ctx._check(lib().rlf_mlp_windows(self.ctx.h, _ptr(y), int(y.shape[0]), float(nsigma),

@@ -1,80 +1,148 @@
-"""The learned grid narrowing end to end: simulate training facets with the
-method, train the network on the GPU with the library's kernels, then on the
-10,000-source config-3 field compare the narrowed fit (windows from the
-network, full-grid fallback) with the plain full-grid fit, the reference for its
-error: RMS(e_window - e_full) <= 1e-3 while evaluating a fraction of the grid.
-A source is refitted on the full grid when a member of its window's 5 % set
-sits on an inner window edge, its window holds no valid grid point, or a
-point of the stride-4 lattice outside the window reaches that set."""
+"""The learned grid narrowing end to end.  The network is trained on the GPU
+with the library's kernels on 200,000 facets simulated with the config-1
+generator, each epoch's targets drawn around the method's own full-grid fits
+(rlf_mlp_posterior_targets); the narrowed fit (windows from the network,
+full-grid fallback by the window rule with its stride-4 lattice check) is
+then compared with the plain full-grid fit, the reference for its error.
+
+What the network gains is measured in time on the benchmark's own field (the
+1000-source SKA-MID-like field, FP64): the narrowed fit, network included,
+must be faster than the full-grid fit at RMS(e_window - e_full) <= 1e-3.
+On the 10,000-source field the error bound is checked and the timing
+reported."""
 import numpy as np
 import pytest
 
-import oracle
 from paper_2203_14071_amd import rlf, surrogate, synth
 from tests import gpu_common as G
+from tests import splitmix
 
 pytestmark = pytest.mark.gpu
 
 
-def test_narrowed_fit_matches_full_fit_on_config3():
+def test_posterior_targets_match_reference_generator():
+    """rlf_mlp_posterior_targets against the published SplitMix64 / Box-Muller
+    definition (tests/splitmix.py): e + kappa s z and ln alpha, row by row;
+    a row without a finite estimate gets (0, 0, ln alpha)."""
     torch = G.torch_cuda()
-    ctx = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED))
+    ctx = rlf.Context(0)
+    net = rlf.Mlp(ctx, max_batch=16)
+    n = 20_000
+    rng = np.random.default_rng(3)
+    e1, e2 = rng.uniform(-0.8, 0.8, n), rng.uniform(-0.8, 0.8, n)
+    s1, s2 = rng.uniform(0.01, 0.3, n), rng.uniform(0.01, 0.3, n)
+    lna = rng.normal(0, 0.3, n).astype(np.float32)
+    e1[7] = np.nan
+    s2[11] = np.inf
+    d = lambda a: G.to_dev(a)
+    out = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
+    seed = 0xC0FFEE123
+    net.posterior_targets(d(e1), d(e2), d(s1), d(s2), d(lna), out, 1.1, seed)
+    ctx.sync()
+    got = out.cpu().numpy()
+    z = splitmix.std_normal(seed, np.arange(2 * n, dtype=np.uint64))
+    ref = np.stack([e1 + 1.1 * s1 * z[0::2], e2 + 1.1 * s2 * z[1::2]], 1).astype(np.float32)
+    bad = np.zeros(n, bool)
+    bad[[7, 11]] = True
+    ref[bad] = 0.0
+    assert np.allclose(got[:, :2], ref, rtol=2e-6, atol=1e-7)
+    assert np.array_equal(got[:, 2], lna)
+    # another seed gives other numbers
+    net.posterior_targets(d(e1), d(e2), d(s1), d(s2), d(lna), out, 1.1, seed + 1)
+    ctx.sync()
+    assert np.mean(np.abs(out.cpu().numpy()[~bad, 0] - got[~bad, 0]) > 1e-6) > 0.99
+    net.free()
+    ctx.close()
+
+
+def _trained(ctx, population):
     net = rlf.Mlp(ctx, max_batch=512)
     net.set_state(surrogate.init_params())
-    x, tg = surrogate.training_set(ctx, net, n_total=200_000, batch_src=20_000, population="config3")
-    hist = surrogate.train(ctx, net, x, tg, epochs=24)
-    print("training losses", [round(h, 3) for h in hist])
+    ts = surrogate.training_set(ctx, net, n_total=200_000, batch_src=20_000, population=population)
+    hist = surrogate.train(ctx, net, ts)
+    print(f"training losses ({population}): first {hist[0]:.3f}, last {hist[-1]:.3f}")
     assert hist[-1] < hist[0]
-    del x, tg
+    del ts
+    G.torch_cuda().cuda.empty_cache()
+    return net
 
+
+def _compare(ctx, net, f, n, reps=5):
+    """(full-grid ms, narrowed ms, RMS de, max |de|, fallback fraction)."""
+    torch = G.torch_cuda()
+    stream = torch.cuda.current_stream()
+    full = G.fit_out_tensors(n, surface=False)
+    nar = G.fit_out_tensors(n, surface=False)
+    w = surrogate.Windowed(ctx, net, n)
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_full = timed(lambda: ctx.fit_sources(f, full))
+    t_nar = timed(lambda: w.fit(f, nar))
+    t_full = min(t_full, timed(lambda: ctx.fit_sources(f, full)))     # both orders
+    a, b = G.host(full), G.host(nar)
+    ok = np.isfinite(a["e1"])
+    assert np.array_equal(ok, np.isfinite(b["e1"]))
+    de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
+    fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
+    return t_full, t_nar, float(np.sqrt(np.mean(de ** 2))), float(np.max(np.abs(de))), fb
+
+
+def test_narrowed_fit_is_faster_on_the_1k_field():
+    torch = G.torch_cuda()
+    mctx = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED))
+    net = _trained(mctx, "config1")
+    params = net.get_state()["params"]
+    net.free()
+    mctx.close()
+
+    ctx = rlf.Context(0, torch.cuda.current_stream().cuda_stream, rlf.params(precision=rlf.RLF_FP64))
+    cfg = synth.CONFIGS[1]
+    o = synth.observation(1)
+    cat = synth.catalogue(cfg, synth.rng(1, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(1, synth.STREAM_NOISE), o.n_rows)
+    obs = G.make_obs(o, nz)
+    ctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
+    catc = G.circular(cat)
+    f = ctx.facets_create(obs, catc)
+    ctx.extract_facets(obs, catc, None, f)
+    net = rlf.Mlp(ctx, max_batch=512)
+    net.set_state(params)
+    t_full, t_nar, rms, mx, fb = _compare(ctx, net, f, cat.n_src)
+    print(f"1k field, FP64: full grid {t_full:.2f} ms, narrowed {t_nar:.2f} ms (x{t_full / t_nar:.2f}), "
+          f"RMS(de) {rms:.2e}, max |de| {mx:.2e}, fallback {fb:.3f}")
+    assert rms <= 1e-3
+    assert t_nar < t_full
+    f.free()
+    net.free()
+    ctx.close()
+
+
+def test_narrowed_fit_on_the_10k_field():
+    mctx = rlf.Context(0, None, rlf.params(precision=rlf.RLF_MIXED))
+    net = _trained(mctx, "config3")
     cfg = synth.CONFIGS[3]
     o = synth.observation(3)
     cat = synth.catalogue(cfg, synth.rng(3, synth.STREAM_CAT))
     nz = synth.noise(cfg, synth.rng(3, synth.STREAM_NOISE), o.n_rows * o.n_chan)
     obs = G.make_obs(o, nz.astype(np.complex64), mixed=True)
-    ctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
+    mctx.model_vis(obs, cat, obs.vis, mode=rlf.RLF_MODEL_ACCUMULATE)
     catc = G.circular(cat)
-    f = ctx.facets_create(obs, catc)
-    ctx.extract_facets(obs, catc, None, f)
-    n = cat.n_src
-    full = G.fit_out_tensors(n, surface=False)
-    ctx.fit_sources(f, full)
-    w = surrogate.Windowed(ctx, net, n)
-    nar = G.fit_out_tensors(n, surface=False)
-    w.fit(f, nar, check_stride=4)
-    ctx.sync()
-    a, b = G.host(full), G.host(nar)
-    win = w.win.cpu().numpy()
-    area = (win[:, 1] - win[:, 0] + 1) * (win[:, 3] - win[:, 2] + 1)
-    ok = np.isfinite(a["e1"]) & np.isfinite(b["e1"])
-    assert np.array_equal(ok, np.isfinite(a["e1"]))
-    de = np.concatenate([b["e1"][ok] - a["e1"][ok], b["e2"][ok] - a["e2"][ok]])
-    rms = float(np.sqrt(np.mean(de ** 2)))
-    fb = float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))
-    print(f"narrowed fit: RMS(de) {rms:.2e}, max |de| {np.max(np.abs(de)):.2e}, fallback {fb:.3f}, "
-          f"mean window {area.mean():.0f} of 6561 grid points")
-    # grid points evaluated: window + lattice outside it, plus the full grid on refits
-    i1, i2, _, _, valid = oracle.e_grid(81, 0.02)
-    lat = valid & ((i1 - 40) % 4 == 0) & ((i2 - 40) % 4 == 0)
-    evals = 0
-    for k in range(n):
-        inside = (i1 >= win[k, 0]) & (i1 <= win[k, 1]) & (i2 >= win[k, 2]) & (i2 <= win[k, 3])
-        evals += np.count_nonzero(valid & inside) + np.count_nonzero(lat & ~inside)
-    evals += np.count_nonzero(b["flags"] & rlf.RLF_FLAG_FALLBACK) * np.count_nonzero(valid)
-    frac = evals / (n * np.count_nonzero(valid))
-    print(f"evaluated {frac:.3f} of the full-grid points")
+    f = mctx.facets_create(obs, catc)
+    mctx.extract_facets(obs, catc, None, f)
+    t_full, t_nar, rms, mx, fb = _compare(mctx, net, f, cat.n_src, reps=3)
+    print(f"10k field, mixed: full grid {t_full:.2f} ms, narrowed {t_nar:.2f} ms (x{t_full / t_nar:.2f}), "
+          f"RMS(de) {rms:.2e}, max |de| {mx:.2e}, fallback {fb:.3f}")
     assert rms <= 1e-3
-    # what the network gains: a share of the sources is fitted on a narrowed
-    # window that the full grid confirms, and fewer grid points are evaluated.
-    # The trained network depends on the last bits of its training facets
-    # (a change in the kernels' FP32 rounding gives another network), and
-    # config-3 posteriors are broad, so the gain is small and moves with such
-    # changes: the bounds leave room for that (current kernels: 8.4 % kept,
-    # 0.978 of the points evaluated).
-    kept = (area < 81 * 81) & ((b["flags"] & rlf.RLF_FLAG_FALLBACK) == 0)
-    print(f"narrowed and kept: {kept.mean():.3f} of the sources")
-    assert kept.mean() >= 0.05
-    assert frac < 0.99
     f.free()
     net.free()
-    ctx.close()
+    mctx.close()

@@ -198,6 +198,70 @@ def valu_probe(iters=8192, blocks=2048):
     return {"clock_hz": CLOCK_HZ, "cus": N_CU, "blocks": blocks, "threads": 256, "iters": iters, "probes": rows}
 
 
+def mlp_flop_per_row(train=True):
+    """GEMM FLOPs of the network per input row (FMA = 2): forward
+    8192x512 + 2 x 512x512 + 512x6 multiply-adds; training adds the weight
+    gradients (the same shapes again) and the gradients of the hidden
+    activations (2 x 512x512 + 512x6; none for the input layer)."""
+    fwd = 8192 * 512 + 2 * 512 * 512 + 512 * 6
+    return 2 * (fwd + (fwd + 2 * 512 * 512 + 512 * 6 if train else 0))
+
+
+def mlp_bench(batches=(512, 4096), steps=20, infer_rows=10_000):
+    """Training-step and inference throughput of the network's BF16 MFMA
+    kernels on random inputs (the shapes of the training and of the
+    10,000-source inference)."""
+    import torch
+    from paper_2203_14071_amd import rlf, surrogate
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    ctx = rlf.Context(0, stream.cuda_stream)
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    res = {"train": [], "inference": None}
+    for b in batches:
+        net = rlf.Mlp(ctx, max_batch=b)
+        net.set_state(surrogate.init_params())
+        x = (0.5 * torch.randn((b, 8192), generator=g, device=dev)).to(torch.bfloat16)
+        tg = 0.3 * torch.randn((b, 3), generator=g, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            net.train_step(x, tg, 1e-4, loss)
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            net.train_step(x, tg, 1e-4, loss)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tf = mlp_flop_per_row(True) * b / (ms * 1e-3) / 1e12
+        res["train"].append({"batch": b, "ms_per_step": round(ms, 4), "gemm_tflops": round(tf, 2),
+                             "frac_of_bf16_peak": round(tf / 2500.0, 4)})
+        log(f"[mlp] train batch {b}: {ms:.3f} ms per step, {tf:.1f} TFLOP/s of GEMM work")
+        net.free()
+    net = rlf.Mlp(ctx, max_batch=512)
+    net.set_state(surrogate.init_params())
+    x = (0.5 * torch.randn((infer_rows, 8192), generator=g, device=dev)).to(torch.bfloat16)
+    y = torch.empty((infer_rows, 6), dtype=torch.float32, device=dev)
+    net.forward(x, y)
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        net.forward(x, y)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tf = mlp_flop_per_row(False) * infer_rows / (ms * 1e-3) / 1e12
+    res["inference"] = {"rows": infer_rows, "ms": round(ms, 4), "gemm_tflops": round(tf, 2),
+                        "frac_of_bf16_peak": round(tf / 2500.0, 4)}
+    log(f"[mlp] forward {infer_rows} rows: {ms:.3f} ms, {tf:.1f} TFLOP/s")
+    net.free()
+    ctx.close()
+    return res
+
+
 def _values(text, typ):
     """Comma-separated list of values; '' or 'none' is the empty list."""
     return [] if text in ("", "none") else [typ(v) for v in text.split(",")]
@@ -233,11 +297,16 @@ def main():
                     help="lattice strides of the lattice-seeded window fit to compare ('' or none = skip)")
     ap.add_argument("--full-frac", type=float, default=0.6,
                     help="windows above this fraction of the grid are fitted on the whole grid")
+    ap.add_argument("--mlp-bench", action="store_true",
+                    help="only time the network's training step and inference (BF16 MFMA) and print its JSON")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only run the VALU issue-rate probe (roofline ceilings) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.mlp_bench:
+        print(json.dumps(mlp_bench()), flush=True)
+        return
     if args.valu_probe:
         print(json.dumps(valu_probe()), flush=True)
         return

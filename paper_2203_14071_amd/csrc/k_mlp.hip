@@ -16,6 +16,7 @@
 // order, so results do not depend on scheduling.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "rlf_internal.h"
@@ -116,6 +117,173 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
+// GEMM with both operands contiguous along k: C[M x N] (FP32, row stride
+// ldc) = sum_k A[m lda + k] B[n ldb + k].  Block tile 128 x 128, k tile 64,
+// four waves each owning a 64 x 64 quarter as 2 x 2
+// v_mfma_f32_32x32x16_bf16 tiles.  Both k tiles are staged [row][k] in LDS
+// (rows padded to 72 BF16, so the eight lanes of one 16-byte read phase hit
+// distinct banks) with 16-byte global loads and LDS stores; the LDS holds two
+// k tiles, and the global loads of tile t+1 are issued before the MFMAs of
+// tile t and stored to the other half after them, so one barrier per tile
+// separates the phases.  Rows beyond M or N and k beyond the slice read as
+// zero (K a multiple of 8, lda and ldb multiples of 8).  grid.z splits K in
+// multiples of 64; with more than one slice each writes its partial product
+// to the workspace and k_reduce_split adds the slices in order.
+constexpr int kTM = 128, kTN = 128, kTK = 64, kLdT = kTK + 8;
+
+__device__ __forceinline__ void nt_load(bf16x8 (&r)[4], const __bf16 *__restrict__ p, int64_t ld, int r0, int nr,
+                                        int k0, int ke) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = threadIdx.x + 256 * j;
+    const int row = c >> 3, kc = (c & 7) * 8;
+    const int gr = r0 + row, gk = k0 + kc;
+    if (gr < nr && gk + 8 <= ke) {
+      r[j] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)gr * ld + gk);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) r[j][e] = (gr < nr && gk + e < ke) ? p[(int64_t)gr * ld + gk + e] : to_bf16(0.0f);
+    }
+  }
+}
+
+__device__ __forceinline__ void nt_store(__bf16 *lds, const bf16x8 (&r)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = threadIdx.x + 256 * j;
+    *reinterpret_cast<bf16x8 *>(lds + (c >> 3) * kLdT + (c & 7) * 8) = r[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmNTArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 sa[2][kTM * kLdT];
+  __shared__ __attribute__((aligned(16))) __bf16 sb[2][kTN * kLdT];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+  const int kper = ((g.K + (int)gridDim.z - 1) / (int)gridDim.z + kTK - 1) / kTK * kTK;
+  const int kb = blockIdx.z * kper, ke = min(g.K, kb + kper);
+  f32x16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  bf16x8 ra[4], rb[4];
+  int buf = 0;
+  if (kb < ke) {
+    nt_load(ra, g.a, g.lda, m0, g.M, kb, ke);
+    nt_load(rb, g.b, g.ldb, n0, g.N, kb, ke);
+    nt_store(sa[0], ra);
+    nt_store(sb[0], rb);
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
+    const bool more = k0 + kTK < ke;
+    if (more) {
+      nt_load(ra, g.a, g.lda, m0, g.M, k0 + kTK, ke);
+      nt_load(rb, g.b, g.ldb, n0, g.N, k0 + kTK, ke);
+    }
+    const __bf16 *A = sa[buf], *B = sb[buf];
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      bf16x8 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *reinterpret_cast<const bf16x8 *>(A + (wm + i * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        fb[j] = *reinterpret_cast<const bf16x8 *>(B + (wn + j * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      nt_store(sa[buf ^ 1], ra);
+      nt_store(sb[buf ^ 1], rb);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  float *outp = gridDim.z > 1 ? g.ws + (int64_t)blockIdx.z * g.M * g.N : g.c;
+  const int64_t ld = gridDim.z > 1 ? g.N : g.ldc;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int n = n0 + wn + j * 32 + (lane & 31);
+        if (m < g.M && n < g.N) outp[(int64_t)m * ld + n] = acc[i][j][r];
+      }
+}
+
+// dst[c][r] = src[r][c] for a BF16 matrix [rows x cols]: 64 x 64 tiles
+// through LDS, four BF16 (8 bytes) per global access when the tile is whole
+// and the row lengths are multiples of 4, else one element per access.
+__global__ __launch_bounds__(256) void k_transpose_bf16(const __bf16 *__restrict__ src, int64_t rows, int64_t cols,
+                                                        __bf16 *__restrict__ dst) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  __shared__ __bf16 t[64][66];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const bool whole = r0 + 64 <= rows && c0 + 64 <= cols && (cols % 4) == 0 && (rows % 4) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0;
+  if (whole) {
+    // 64 rows x 16 groups of 4 columns: 4 per thread
+    for (int q = threadIdx.x; q < 64 * 16; q += 256) {
+      const int i = q >> 4, c4 = (q & 15) * 4;
+      const bf16x4 v = *reinterpret_cast<const bf16x4 *>(src + (r0 + i) * cols + c0 + c4);
+      for (int e = 0; e < 4; ++e) t[i][c4 + e] = v[e];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * 16; q += 256) {
+      const int j = q >> 4, r4 = (q & 15) * 4;           // output row j = source column c0 + j
+      bf16x4 v;
+      for (int e = 0; e < 4; ++e) v[e] = t[r4 + e][j];
+      *reinterpret_cast<bf16x4 *>(dst + (c0 + j) * rows + r0 + r4) = v;
+    }
+    return;
+  }
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < rows && c < cols) ? src[r * cols + c] : to_bf16(0.0f);
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) dst[c * rows + r] = t[tx][i];
+  }
+}
+
+// Column sums in two deterministic steps: block (x, y) sums its slice of rows
+// for 64 columns (four row groups, added in order) into part[y][col]; then
+// each column adds the slices in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *d, int64_t rows, int cols, int64_t per,
+                                                     float *part) {
+  __shared__ float sh[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
+  float acc = 0.0f;
+  if (col < cols)
+    for (int64_t r = r0 + rg; r < r1; r += 4) acc += d[r * cols + col];
+  sh[rg][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (rg == 0 && col < cols)
+    part[(int64_t)blockIdx.y * cols + col] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+// One wave per column: lane j adds slices j, j + 64, ... in order, then the
+// lanes are added by a fixed butterfly (the same sum on every run).
+__global__ __launch_bounds__(256) void k_colsum_join(const float *part, int slices, int cols, float *db) {
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= cols) return;                                   // uniform per wave
+  float acc = 0.0f;
+  for (int y = lane; y < slices; y += 64) acc += part[(int64_t)y * cols + col];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d);
+  if (lane == 0) db[col] = acc;
+}
+
 // c[m][n] = sum over slices z = 0, 1, ... of ws[z][m][n], in that order
 __global__ __launch_bounds__(256) void k_reduce_split(const float *ws, int split, int M, int N, float *c,
                                                       int64_t ldc) {
@@ -180,19 +348,6 @@ __global__ __launch_bounds__(256) void k_gelu_back(const float *dh, const float 
     dz[i] = v;
     dzb[i] = to_bf16(v);
   }
-}
-
-// db[col] = sum over rows of d[row][col]: one block per column group of 64
-__global__ __launch_bounds__(256) void k_colsum(const float *d, int64_t rows, int cols, float *db) {
-  __shared__ float sh[4][64];
-  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int rg = threadIdx.x >> 6;
-  float acc = 0.0f;
-  if (col < cols)
-    for (int64_t r = rg; r < rows; r += 4) acc += d[r * cols + col];
-  sh[rg][threadIdx.x & 63] = acc;
-  __syncthreads();
-  if (rg == 0 && col < cols) db[col] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n,
@@ -326,8 +481,31 @@ hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *d
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64), dim3(256), 0, st, d, rows, cols, db);
+hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
+                         hipStream_t st) {
+  // slices of at least 32 rows, at most 256 of them (one block per slice and 64 columns)
+  const int64_t slices = std::max<int64_t>(1, std::min<int64_t>({256, (rows + 31) / 32, ws_floats / std::max(1, cols)}));
+  const int64_t per = (rows + slices - 1) / slices;
+  const int nsl = (int)((rows + per - 1) / per);
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nsl), dim3(256), 0, st, d, rows, cols, per, ws);
+  hipLaunchKernelGGL(k_colsum_join, dim3((cols + 3) / 4), dim3(256), 0, st, ws, nsl, cols, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st) {
+  if (g.K % 8 || g.lda % 8 || g.ldb % 8) return hipErrorInvalidValue;
+  if (split_k > 1 && (!g.ws || (int64_t)split_k * g.M * g.N > g.ws_floats)) return hipErrorInvalidValue;
+  const dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM, split_k > 1 ? split_k : 1);
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, g);
+  if (split_k > 1)
+    hipLaunchKernelGGL(k_reduce_split, dim3(grid_for((int64_t)g.M * g.N)), dim3(256), 0, st, g.ws, split_k, g.M, g.N,
+                       g.c, g.ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const __bf16 *src, int64_t rows, int64_t cols, __bf16 *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64)), dim3(256), 0,
+                     st, src, rows, cols, dst);
   return hipGetLastError();
 }
 

@@ -272,6 +272,20 @@ struct GemmArgs {
   int64_t ws_floats;
 };
 
+// C[M x N] (FP32, row stride ldc) = sum_k A[m lda + k] B[n ldb + k], A and B
+// BF16 contiguous along k.
+struct GemmNTArgs {
+  const __bf16 *a;
+  int64_t lda;
+  const __bf16 *b;
+  int64_t ldb;
+  float *c;
+  int64_t ldc;
+  int32_t M, N, K;
+  float *ws;                 // split-K partials [split x M x N]
+  int64_t ws_floats;
+};
+
 struct FeatureArgs {
   int32_t n_src;
   const int64_t *offsets;
@@ -317,7 +331,10 @@ hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int col
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st);
 hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *dz, __bf16 *dzb, hipStream_t st);
-hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, hipStream_t st);
+hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
+                         hipStream_t st);
+hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st);
+hipError_t launch_transpose_bf16(const __bf16 *src, int64_t rows, int64_t cols, __bf16 *dst, hipStream_t st);
 hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n, float lr, int64_t step,
                        hipStream_t st);
 hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);

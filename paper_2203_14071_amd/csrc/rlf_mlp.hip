@@ -36,8 +36,13 @@ struct rlf_mlp {
   float *z[3] = {nullptr, nullptr, nullptr};
   __bf16 *h[3] = {nullptr, nullptr, nullptr};
   float *y = nullptr, *cbuf = nullptr, *dy = nullptr, *dh = nullptr, *dz = nullptr;
-  float *ws = nullptr;                       // split-K partial products
+  float *ws = nullptr;                       // split-K partial products, column-sum slices
   __bf16 *dyb = nullptr, *dzb = nullptr;
+  // k-contiguous operands of the NT GEMM: the BF16 weights transposed per
+  // layer (W_l^T [out x in] at the offsets of W_l), and per batch the layer
+  // input and the gradient dZ transposed ([in x rows], [512 x rows])
+  __bf16 *wbt = nullptr;
+  __bf16 *xt = nullptr, *ht = nullptr, *dzt = nullptr;
 };
 
 namespace {
@@ -65,6 +70,10 @@ void mlp_release(rlf_mlp *n) {
   dfree(n->dyb);
   dfree(n->dzb);
   dfree(n->ws);
+  dfree(n->wbt);
+  dfree(n->xt);
+  dfree(n->ht);
+  dfree(n->dzt);
 }
 
 constexpr int kMaxSplitBlocks = 512;                  // tiles x K slices
@@ -100,6 +109,46 @@ int gemm(rlf_mlp *net, const __bf16 *a, int64_t sam, int64_t sak, const __bf16 *
   return RLF_OK;
 }
 
+// Split of K for the NT GEMM: until the grid fills the CUs twice over, with
+// slices of at least 128 k.
+int split_nt(int M, int N, int K) {
+  const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  int s = 1;
+  while (tiles * s * 2 <= kMaxSplitBlocks && K / (s * 2) >= 128 && (int64_t)(s * 2) * M * N <= kWsFloats) s *= 2;
+  return s;
+}
+
+// C[M x N] (row stride ldc) = sum_k A[m lda + k] B[n ldb + k].
+int gemm_nt(rlf_mlp *net, const __bf16 *a, int64_t lda, const __bf16 *b, int64_t ldb, float *out, int64_t ldc, int M,
+            int N, int K) {
+  GemmNTArgs ga{};
+  ga.a = a;
+  ga.lda = lda;
+  ga.b = b;
+  ga.ldb = ldb;
+  ga.c = out;
+  ga.ldc = ldc;
+  ga.M = M;
+  ga.N = N;
+  ga.K = K;
+  ga.ws = net->ws;
+  ga.ws_floats = kWsFloats;
+  hipError_t e = launch_gemm_nt(ga, split_nt(M, N, K), net->c->stream);
+  if (e != hipSuccess) return hip_fail(net->c, e, "gemm_nt launch");
+  return RLF_OK;
+}
+
+// The transposed BF16 weights W_l^T [out x in] from W_l [in x out].
+int update_wbt(rlf_mlp *n) {
+  const int64_t offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+  const int64_t din[4] = {kIn, kHid, kHid, kHid}, dout[4] = {kHid, kHid, kHid, kOut};
+  for (int l = 0; l < 4; ++l) {
+    hipError_t e = launch_transpose_bf16(n->wb + offW[l], din[l], dout[l], n->wbt + offW[l], n->c->stream);
+    if (e != hipSuccess) return hip_fail(n->c, e, "weight transpose launch");
+  }
+  return RLF_OK;
+}
+
 // Forward of rows [0, nb) of x into the layer buffers; y_out receives the outputs.
 int forward_chunk(rlf_mlp *n, const __bf16 *x, int nb, float *y_out) {
   rlf_ctx *c = n->c;
@@ -107,7 +156,8 @@ int forward_chunk(rlf_mlp *n, const __bf16 *x, int nb, float *y_out) {
   int kin = kIn;
   const int64_t offW[3] = {kOffW1, kOffW2, kOffW3}, offB[3] = {kOffB1, kOffB2, kOffB3};
   for (int l = 0; l < 3; ++l) {
-    if (int e = gemm(n, hin, kin, 1, n->wb + offW[l], kHid, 1, n->cbuf, nb, kHid, kin)) return e;
+    // z = h W: rows of h and of W^T are both contiguous along the contraction
+    if (int e = gemm_nt(n, hin, kin, n->wbt + offW[l], kin, n->cbuf, kHid, nb, kHid, kin)) return e;
     hipError_t e = launch_bias_act(n->cbuf, n->w + offB[l], nb, kHid, n->z[l], n->h[l], 1, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bias/GELU launch");
     hin = n->h[l];
@@ -154,10 +204,15 @@ int rlf_mlp_create(rlf_ctx *c, int64_t max_batch, rlf_mlp **out) {
     if ((rc = dalloc(c, &n->dz, B * kHid))) break;
     if ((rc = dalloc(c, &n->dzb, B * kHid))) break;
     if ((rc = dalloc(c, &n->ws, kWsFloats))) break;
+    if ((rc = dalloc(c, &n->wbt, kParams))) break;
+    if ((rc = dalloc(c, &n->xt, B * kIn))) break;
+    if ((rc = dalloc(c, &n->ht, B * kHid))) break;
+    if ((rc = dalloc(c, &n->dzt, B * kHid))) break;
     hipError_t e = hipMemset(n->w, 0, sizeof(float) * kParams);
     if (e == hipSuccess) e = hipMemset(n->m, 0, sizeof(float) * kParams);
     if (e == hipSuccess) e = hipMemset(n->v, 0, sizeof(float) * kParams);
     if (e == hipSuccess) e = hipMemset(n->wb, 0, sizeof(__bf16) * kParams);
+    if (e == hipSuccess) e = hipMemset(n->wbt, 0, sizeof(__bf16) * kParams);
     if (e != hipSuccess) rc = hip_fail(c, e, "rlf_mlp_create: clearing parameters");
   } while (0);
   if (rc) {
@@ -190,6 +245,7 @@ int rlf_mlp_set_state(rlf_mlp *n, const float *params_host, const float *m_host,
   else HIPCHK(c, hipMemset(n->v, 0, sizeof(float) * kParams));
   n->step = step;
   HIPCHK(c, launch_to_bf16(n->w, n->wb, kParams, c->stream));
+  if (int e = update_wbt(n)) return e;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RLF_OK;
 }
@@ -350,20 +406,32 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   HIPCHK(c, launch_head(n->y, target, nb, n->dy, n->dyb, loss, c->stream));
   // output layer: dW4 = h3^T dY, db4 = sum dY, dh3 = dY W4^T
   if (int e = gemm(n, n->h[2], 1, kHid, n->dyb, kOut, 1, n->g + kOffW4, kHid, kOut, nb)) return e;
-  HIPCHK(c, launch_colsum(n->dy, nb, kOut, n->g + kOffB4, c->stream));
+  HIPCHK(c, launch_colsum(n->dy, nb, kOut, n->g + kOffB4, n->ws, kWsFloats, c->stream));
   if (int e = gemm(n, n->dyb, kOut, 1, n->wb + kOffW4, 1, kOut, n->dh, nb, kHid, kOut)) return e;
   const int64_t offW[3] = {kOffW1, kOffW2, kOffW3}, offB[3] = {kOffB1, kOffB2, kOffB3};
+  // the NT GEMM needs the batch dimension in multiples of 8 for the weight gradients
+  const bool nt_rows = nb % 8 == 0;
   for (int l = 2; l >= 0; --l) {
     HIPCHK(c, launch_gelu_back(n->dh, n->z[l], (int64_t)nb * kHid, n->dz, n->dzb, c->stream));
-    HIPCHK(c, launch_colsum(n->dz, nb, kHid, n->g + offB[l], c->stream));
+    HIPCHK(c, launch_colsum(n->dz, nb, kHid, n->g + offB[l], n->ws, kWsFloats, c->stream));
     const __bf16 *hin = l == 0 ? xb : n->h[l - 1];
     const int kin = l == 0 ? kIn : kHid;
-    if (int e = gemm(n, hin, 1, kin, n->dzb, kHid, 1, n->g + offW[l], kin, kHid, nb)) return e;
+    if (nt_rows) {
+      // dW = h^T dZ with both operands transposed to [features x rows]
+      __bf16 *hin_t = l == 0 ? n->xt : n->ht;
+      HIPCHK(c, launch_transpose_bf16(hin, nb, kin, hin_t, c->stream));
+      HIPCHK(c, launch_transpose_bf16(n->dzb, nb, kHid, n->dzt, c->stream));
+      if (int e = gemm_nt(n, hin_t, nb, n->dzt, nb, n->g + offW[l], kHid, kin, kHid, nb)) return e;
+    } else {
+      if (int e = gemm(n, hin, 1, kin, n->dzb, kHid, 1, n->g + offW[l], kin, kHid, nb)) return e;
+    }
+    // dh = dZ W^T: rows of dZ and of W both run along the output index
     if (l > 0)
-      if (int e = gemm(n, n->dzb, kHid, 1, n->wb + offW[l], 1, kHid, n->dh, nb, kHid, kHid)) return e;
+      if (int e = gemm_nt(n, n->dzb, kHid, n->wb + offW[l], kHid, n->dh, kHid, nb, kHid, kHid)) return e;
   }
   n->step += 1;
   HIPCHK(c, launch_adam(n->w, n->wb, n->g, n->m, n->v, kParams, lr, n->step, c->stream));
+  if (int e = update_wbt(n)) return e;
   return RLF_OK;
 }
 

@@ -53,34 +53,55 @@ MODEL_FLOP_PAIR = 19
 #   likelihood (k_fit + k_estimate): fetch 154.8 + 150.2 / 78.9 + 150.0 MB,
 #     write 51.3 + 0.3 / 51.3 + 0.3 MB
 #   sky model (k_model): fetch 372.9 / 298.3 MB, write 148.3 / 74.1 MB
-TRAFFIC_BYTES = {"fp64": {"extract": 2830.3e6, "fit": 356.6e6, "model": 521.2e6},
-                 "mixed": {"extract": 2175.7e6, "fit": 280.5e6, "model": 372.4e6}}
-# VALU roofline in lane-slots: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s,
-# with the method's necessary work per unit priced as in the hot-path scope's
-# cost model (FP64 FMA and FP32 add/mul/FMA 1 slot, transcendentals 4):
-#   sky-model DFT, per (visibility, source): phase 5, cvt 1, sin + cos +
-#     rsqrt 12, shape form 6, x 1, r^3 S 3, accumulate 2               = 30
-#   extraction, per (visibility, source): phase 6, cell index 6, sincos +
-#     rsqrt 12, complex rotation 4, own model 9, weight + accumulate 5 = 42
-#   likelihood, per (cell, e point, knot): x 1, rsqrt 4, r^3 2, D and M 3,
-#     the quadratic form 6 per (cell, e point) over the 20 knots 0.3   = 10.3
-#     (+1 for the blocked FP32 sums of the mixed form)                 = 11.3
+TRAFFIC_BYTES = {"fp64": {"extract": 2812.0e6, "fit": 356.5e6, "model": 520.9e6},
+                 "mixed": {"extract": 2173.6e6, "fit": 277.4e6, "model": 372.9e6}}
+# VALU roofline in lane-slots: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
+# Work per unit = the method's necessary operations in each form (not a
+# compiled count), priced with gfx950's measured rates (the VALU probe,
+# probe/valu_probe.hip): FP64 and FP32 add / mul / FMA / conversions 1 slot;
+# v_rsq_f64 4 (it issues at a quarter of the FMA rate); FP32 transcendentals
+# (v_sin / v_cos / v_rsq_f32) 1 (mixed with >= 4 other operations they issue
+# at the plain FMA stream's rate: marginal cost 1.04 slots); FP64 sin and cos,
+# which have no instruction, 4 each plus 2 for the reduction to one turn.
+# Products formed once per visibility (u^2, uv, v^2, shared by every source)
+# or once per (cell, e point) (the quadratic form, shared by the knots) are
+# counted where they are formed.
 SLOT_PEAK = 256 * 64 * 2.4e9
-SLOTS = {"fp64": {"extract": 42.0, "fit": 10.3, "model": 30.0},
-         "mixed": {"extract": 42.0, "fit": 11.3, "model": 30.0}}
-# VALU wave-instructions per launch at this workload (SQ_INSTS_VALU, rocprofv3,
-# profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md), for the issue rate, and
-# the VALU probe (probe/valu_probe.hip) whose instruction stream bounds each
-# kernel's: FP64 kernels by the FP64 FMA stream (the likelihood, one
-# v_rsq_f64 in ten instructions, by the stream with one in eight), the mixed
-# ones by FP32 FMA streams with one FP32 transcendental in six or four
-# (transcendentals co-issue, so such a stream issues above one instruction
-# per CU per cycle)
-VALU_INSTR = {"fp64": {"extract": 5.969e9, "fit": 5.781e9, "model": 4.236e9},
-              "mixed": {"extract": 4.745e9, "fit": 4.853e9, "model": 2.321e9}}
-CEILING_PROBE = {"fp64": {"extract": "fma_f64", "fit": "rsq_f64+2cvt+add+4fma_f64", "model": "fma_f64"},
-                 "mixed": {"extract": "rsq_f32+add+4fma_f32", "fit": "rsq_f32+add+4fma_f32",
-                           "model": "rsq_f32+add+2fma_f32"}}
+SLOT_ITEMS = {
+    "fp64": {
+        # per (visibility, source) pair
+        "model": {"phase 3 FMA": 3, "reduction to one turn": 2, "sin + cos": 8, "shape form 3 FMA": 3,
+                  "rsqrt": 4, "cube and flux 3": 3, "accumulate 2 FMA": 2},
+        "extract": {"phase 3 FMA": 3, "reduction to one turn": 2, "sin + cos": 8,
+                    "cell index 2 mul + 2 rint + key": 5, "cell test": 1, "shape form 3 FMA": 3,
+                    "rsqrt": 4, "cube 2": 2, "rotation + own model + accumulate 5 FMA": 5, "weight sum": 1},
+        # per (cell, e point, knot)
+        "fit": {"profile argument": 1, "rsqrt": 4, "cube 2": 2, "D and M 3": 3,
+                "quadratic form 6 per (cell, e point) over 20 knots": 0.3},
+    },
+    "mixed": {
+        "model": {"phase 3 FMA (FP64)": 3, "fractional turn": 1, "cvt": 1, "sin + cos": 2,
+                  "shape form 3 FMA": 3, "rsqrt": 1, "cube and flux 3": 3, "accumulate 2 FMA": 2},
+        "extract": {"phase 3 FMA (FP64)": 3, "fractional turn": 1, "cvt": 1, "sin + cos": 2,
+                    "cell index 2 mul + 2 rint + key": 5, "cell test": 1, "rotation 4": 4,
+                    "shape form 3 FMA": 3, "rsqrt": 1, "cube 2": 2, "weight x flux": 1, "own model add": 1,
+                    "widen 2 cvt": 2, "accumulate 2 FMA (FP64)": 2, "weight sum": 1},
+        "fit": {"profile argument": 1, "rsqrt": 1, "cube 2": 2, "D and M 3": 3,
+                "quadratic form 6 per (cell, e point) over 20 knots": 0.3,
+                "widening of the 32-cell FP32 sums (4 per 32 cells)": 0.125},
+    },
+}
+SLOTS = {f: {k: round(sum(v.values()), 3) for k, v in d.items()} for f, d in SLOT_ITEMS.items()}
+# VALU work per launch at this workload and the kernel's clock under load
+# (rocprofv3: SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64, GRBM_GUI_ACTIVE / 8 XCDs /
+# duration; profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md), for the issue
+# rate: slots = VALU instructions with each v_rsq_f64 counted 4, per CU per
+# cycle at that clock.  The VALU probe (probe/valu_probe.hip, run by the
+# benchmark) measures what instruction streams of each kind reach.
+VALU_WORK = {"fp64": {"extract": (5.969e9, 1.48e8, 2.233e9), "fit": (5.750e9, 5.90e8, 2.315e9),
+                      "model": (4.236e9, 1.45e8, 2.049e9)},
+             "mixed": {"extract": (4.745e9, 0.0, 2.331e9), "fit": (4.853e9, 4.16e6, 2.348e9),
+                       "model": (2.321e9, 0.0, 2.242e9)}}
 
 
 def log(*a):
@@ -198,6 +219,67 @@ def valu_probe(iters=8192, blocks=2048):
     return {"clock_hz": CLOCK_HZ, "cus": N_CU, "blocks": blocks, "threads": 256, "iters": iters, "probes": rows}
 
 
+# Kernel-mix probes (probe/valu_probe.hip): the kernels' own inner loops on
+# cache-resident synthetic data; name, the kernel roofline they bound
+# (form, stage), items per pass (the field's 1000 sources; its mean of 296
+# cells per facet), passes.  The grid is 32 times what the chip holds at
+# once: a grid of one round (2048 blocks) measured 4-25 % lower rates (its
+# blocks do not spread evenly over the CUs), grids of 8 and 32 rounds agree
+# within 2 %.
+MIX_PROBES = [("sky-model term, FP64 (sum_f64)", ("fp64", "model"), 1000, 1),
+              ("sky-model term, mixed (sum_mixed)", ("mixed", "model"), 1000, 1),
+              ("likelihood cell sums, FP64, 20 knots (cell_sums_f64)", ("fp64", "fit"), 296, 1),
+              ("likelihood cell sums, mixed, 2 x 10 knots (cell_sums_f32)", ("mixed", "fit"), 296, 1)]
+
+
+def mix_probe(blocks=65536):
+    """Units per second that the sky-model and likelihood kernels' own
+    instruction streams reach when their data is free (no visibility or
+    output traffic): the ceiling each of those kernels is measured against."""
+    import ctypes
+    from paper_2203_14071_amd import build
+    L = ctypes.CDLL(build.PROBE_LIB)
+    L.mix_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]
+    assert L.mix_probe_count() == len(MIX_PROBES)
+    rows = []
+    for op, (name, (form, stage), n_items, iters) in enumerate(MIX_PROBES):
+        ms, hz, units = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = L.mix_probe_run(op, blocks, iters, n_items, 5, ctypes.byref(ms), ctypes.byref(hz), ctypes.byref(units))
+        if rc != 0:
+            raise RuntimeError(f"kernel-mix probe {name}: HIP error {rc}")
+        ups = units.value / (ms.value * 1e-3)
+        rows.append({"probe": name, "form": form, "stage": stage, "items_per_pass": n_items, "passes": iters,
+                     "ms": round(ms.value, 4), "units_per_s": float(f"{ups:.5g}"),
+                     "shader_clock_hz": round(hz.value, -6)})
+        log(f"[mix] {name}: {ms.value:.3f} ms, {ups:.4g} units/s; clock {hz.value / 1e9:.3f} GHz")
+    return rows
+
+
+def attach_mix_ceilings(res, rows):
+    """Each sky-model and likelihood roofline gets its own-mix ceiling: the
+    kernel's units/s against the probe's (a fraction <= 1 means the kernel
+    runs at or below the rate its own instruction stream allows)."""
+    by = {(r["form"], r["stage"]): r for r in rows}
+
+    def attach(form, kr):
+        for stage, d in kr.items():
+            r = by.get((form, stage))
+            if r is None or "units_per_s" not in d:
+                continue
+            d["own_mix_ceiling"] = {"probe": r["probe"], "units_per_s": r["units_per_s"],
+                                    "kernel_units_per_s": d["units_per_s"],
+                                    "frac": round(d["units_per_s"] / r["units_per_s"], 4)}
+
+    attach(res["config"]["precision"], res["kernel_rooflines"])
+    res["roofline"] = dict(res["kernel_rooflines"][res["roofline"]["stage"]])
+    pf = res.get("precision_form")
+    if pf:
+        attach(pf["precision"], pf["kernel_rooflines"])
+        pf["roofline"] = dict(pf["kernel_rooflines"][pf["roofline"]["stage"]])
+
+
 def mlp_flop_per_row(train=True):
     """GEMM FLOPs of the network per input row (FMA = 2): forward
     8192x512 + 2 x 512x512 + 512x6 multiply-adds; training adds the weight
@@ -308,7 +390,9 @@ def main():
         print(json.dumps(mlp_bench()), flush=True)
         return
     if args.valu_probe:
-        print(json.dumps(valu_probe()), flush=True)
+        v = valu_probe()
+        v["kernel_mix"] = mix_probe()
+        print(json.dumps(v), flush=True)
         return
     if args.copy_calibration:
         import torch
@@ -374,22 +458,15 @@ def main():
         rows = kscan.run(_values(args.kscan, int), log=log)
         res["facet_size_scan"] = {
             "what": "1000 single sources, 10-200 uJy, noise for SNR 19 at 10 uJy, config-1 coverage; "
-                    "e_measured - e_true = m e_true + c over good fits (Sec. 4.2)",
+                    "e_measured - e_true = m e_true + c over good fits (Sec. 4.1)",
             "paper_context": "K = 38: m1 = 0.0366 +- 0.0028, m2 = 0.0731 +- 0.0026, 0.3 % bad (their data and fit)",
             "rows": rows, "s": round(time.perf_counter() - t0, 2)}
-    # the VALU issue ceilings of the kernels' instruction streams, measured here
+    # what VALU instruction streams of each kind, and the kernels' own inner
+    # loops, reach on this chip, measured here
     try:
-        probe = valu_probe()
-        res["valu_ceilings"] = probe
-        rates = {r["probe"]: r["wave_instr_per_cu_cycle"] for r in probe["probes"]}
-        blocks = [res["kernel_rooflines"], res.get("precision_form", {}).get("kernel_rooflines", {}),
-                  {"_": res["roofline"]}, {"_": res.get("precision_form", {}).get("roofline", {})}]
-        for blk in blocks:
-            for kr in blk.values():
-                iss = kr.get("issue")
-                if iss and iss["ceiling_probe"] in rates:
-                    iss["ceiling"] = rates[iss["ceiling_probe"]]
-                    iss["frac_of_ceiling"] = round(iss["wave_instr_per_cu_cycle"] / iss["ceiling"], 4)
+        res["valu_ceilings"] = valu_probe()
+        res["valu_ceilings"]["kernel_mix"] = mix_probe()
+        attach_mix_ceilings(res, res["valu_ceilings"]["kernel_mix"])
     except (OSError, RuntimeError) as e:
         log(f"[bench] VALU probe not run: {e}")
     if cpu is not None:
@@ -830,16 +907,22 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
         ach = slots / (ms * 1e-3) / 1e12
         fl = flop[k] / (ms * 1e-3) / 1e12
         kernels[k] = {
-            "kernel": names[k], "bound": "alu", "achieved": round(ach, 3), "peak": round(SLOT_PEAK / 1e12, 3),
+            "kernel": names[k], "stage": k, "bound": "alu", "achieved": round(ach, 3), "peak": round(SLOT_PEAK / 1e12, 3),
             "unit": "T VALU lane-slots/s", "frac": round(ach * 1e12 / SLOT_PEAK, 4),
             "traffic": TRAFFIC_BYTES[precision][k],
             "basis": f"{SLOTS[precision][k]} lane-slots per {unit_names[k]} x {units[k]:.6g} units / "
                      f"{ms:.3f} ms; peak 256 CUs x 64 lanes x 2.4 GHz",
+            "slots_per_unit": SLOT_ITEMS[precision][k],
+            "units_per_s": float(f"{units[k] / (ms * 1e-3):.5g}"),
             "flop_basis": {"achieved": round(fl, 3), "peak": peak_flop, "unit": "TFLOP/s",
                            "frac": round(fl / peak_flop, 4), "algorithmic_flop": flop[k]},
-            "issue": {"valu_wave_instr": VALU_INSTR[precision][k],
-                      "wave_instr_per_cu_cycle": round(VALU_INSTR[precision][k] / (ms * 1e-3) / (CLOCK_HZ * N_CU), 4),
-                      "ceiling_probe": CEILING_PROBE[precision][k]},
+            "issue": {"valu_wave_instr": VALU_WORK[precision][k][0], "rsq_f64": VALU_WORK[precision][k][1],
+                      "clock_under_load_hz": VALU_WORK[precision][k][2],
+                      "slots_per_cu_cycle_at_that_clock": round(
+                          (VALU_WORK[precision][k][0] + 3 * VALU_WORK[precision][k][1]) /
+                          (ms * 1e-3) / (VALU_WORK[precision][k][2] * N_CU), 4),
+                      "wave_instr_per_cu_cycle_at_2p4ghz": round(VALU_WORK[precision][k][0] / (ms * 1e-3) /
+                                                                 (CLOCK_HZ * N_CU), 4)},
         }
     dominant = max(("extract", "fit", "model"), key=lambda k: stage_ms[stage_idx[k]])
     roofline = dict(kernels[dominant])

@@ -25,6 +25,7 @@
 // registers; the n_pos values of a cell come in through scalar loads (one
 // row of G per cell), so a (cell, point, knot) costs the profile (6 ops), M
 // (2) and one FMA per offset, plus the quadratic form once per knot block.
+#include "rlf_cellsums.h"
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
 
@@ -32,7 +33,7 @@ namespace rlf {
 
 namespace {
 
-constexpr int kBlock = 32;
+constexpr int kBlock = kCellBlock;
 constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
 
 // Knots per pass over the cells: the mixed form with 20 knots takes them in
@@ -41,28 +42,6 @@ constexpr double kLnPowM32Scale = 0.40546510810816438198;   // ln(3/2)
 // faster); the FP64 form is faster in one pass.
 template <int R, bool kMixed>
 constexpr int knots_per_pass() { return (kMixed && R == 20) ? 10 : R; }
-
-// FP64 sums over cells [cb, ce) of one grid point for KP knots (the first
-// n_use of them): D_k += W Re(Vbar) f, M_k += W f^2 with f = (2/3) f_c.
-template <int KP>
-__device__ __forceinline__ void cell_sums_f64(const double4 *__restrict__ cells, int64_t cb, int64_t ce, double a11,
-                                              double a12, double a22, const double *sk, int n_use, double *D,
-                                              double *M) {
-  for (int64_t c = cb; c < ce; ++c) {
-    const double4 cl = cells[c];
-    const double ku = fma(a11, cl.x, a12 * cl.y);
-    const double kv = fma(a12, cl.x, a22 * cl.y);
-    const double q = fma(ku, ku, kv * kv);
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      if (k < n_use) {
-        const double f = pow_m32_f64(fma(sk[k], q, 1.0));           // (2/3) f_c
-        D[k] = fma(cl.w, f, D[k]);
-        M[k] = fma(cl.z * f, f, M[k]);
-      }
-    }
-  }
-}
 
 // ln L(e) of source s at (e1, e2), |e| < 1; NaN for an empty facet.
 template <int R, bool kExact, bool kMixed>
@@ -95,36 +74,7 @@ __device__ __forceinline__ double loglike_e(const FitArgs &a, int num_r_arg, int
       float sk[KP];
 #pragma unroll
       for (int k = 0; k < KP; ++k) sk[k] = k0 + k < num_r ? (float)(a.sk[k0 + k] * g) : 0.0f;
-      const float4 *__restrict__ cells = a.fit32;
-      auto block = [&](int64_t cb, int n) {
-        float d[KP], m[KP];
-#pragma unroll
-        for (int k = 0; k < KP; ++k) d[k] = m[k] = 0.0f;
-        for (int t = 0; t < n; ++t) {
-          const float4 cl = cells[cb + t];
-          const float ku = fmaf(a11, cl.x, a12 * cl.y);
-          const float kv = fmaf(a12, cl.x, a22 * cl.y);
-          const float q = fmaf(ku, ku, kv * kv);
-#pragma unroll
-          for (int k = 0; k < KP; ++k) {
-            if (k0 + k < num_r) {
-              const float r = __builtin_amdgcn_rsqf(fmaf(sk[k], q, 1.0f));
-              const float f = r * r * r;
-              d[k] = fmaf(cl.w, f, d[k]);
-              m[k] = fmaf(cl.z * f, f, m[k]);
-            }
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-          D[k] += (double)d[k];
-          M[k] += (double)m[k];
-        }
-      };
-      int64_t cb = c0;
-#pragma clang loop unroll(disable)
-      for (; cb + kBlock <= c1; cb += kBlock) block(cb, kBlock);
-      if (cb < c1) block(cb, (int)(c1 - cb));
+      cell_sums_f32<KP>(a.fit32, c0, c1, a11, a12, a22, sk, num_r - k0, D, M);
     }
     // ln(w_k L(e, alpha_k)) in place of D; FP64 form: D and M carry (2/3)
     // and (4/9) of their values, so the ratio term is unchanged and ln M is

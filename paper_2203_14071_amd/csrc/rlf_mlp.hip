@@ -109,12 +109,13 @@ int gemm(rlf_mlp *net, const __bf16 *a, int64_t sam, int64_t sak, const __bf16 *
   return RLF_OK;
 }
 
-// Split of K for the NT GEMM: until the grid fills the CUs twice over, with
-// slices of at least 128 k.
+// Split of K for the NT GEMM: until the grid fills the 256 CUs once, with
+// slices of at least 512 (each slice's partial product is written and read
+// back once by the reduction, which costs more than it saves below that).
 int split_nt(int M, int N, int K) {
   const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
   int s = 1;
-  while (tiles * s * 2 <= kMaxSplitBlocks && K / (s * 2) >= 128 && (int64_t)(s * 2) * M * N <= kWsFloats) s *= 2;
+  while (tiles * s * 2 <= 256 && K / (s * 2) >= 512 && (int64_t)(s * 2) * M * N <= kWsFloats) s *= 2;
   return s;
 }
 

@@ -1,4 +1,4 @@
-"""Facet-size tuning experiment (Sec. 4.2): fit a population of single
+"""Facet-size tuning experiment (Sec. 4.1): fit a population of single
 sources on the SKA-MID-like coverage for several facet-size factors K and
 measure the multiplicative and additive biases of the linear model
 e_measured - e_true = m e_true + c (per component), and the number of bad

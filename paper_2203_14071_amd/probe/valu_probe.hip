@@ -7,8 +7,22 @@
 // groups are single instruction types (FP64 / FP32 FMA, v_rsq_f64, v_rsq_f32,
 // v_sin_f32, v_exp_f32) and mixes of one transcendental with k FMAs, which
 // show whether transcendentals issue alongside other VALU work.
+//
+// A second set ("kernel-mix" probes) runs the library kernels' own inner
+// loops, the shared device functions of the sky model (sum_f64, sum_mixed)
+// and of the likelihood (cell_sums_f64, cell_sums_f32), on synthetic
+// sources and cells in small cache-resident arrays read as the kernels
+// read them (wave-uniform scalar loads).  Their time is that of the
+// kernels' own instruction streams without the kernels' visibility and
+// output traffic: the ceiling each kernel is measured against.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <vector>
+
+#include "rlf_cellsums.h"
+#include "rlf_internal.h"
+#include "rlf_sky.h"
 
 namespace {
 
@@ -119,6 +133,148 @@ hipError_t launch_op(int op, int blocks, int64_t iters, float *s32, double *s64,
 
 }  // namespace
 
+namespace {
+
+enum MixOp : int { kMixSkyF64 = 0, kMixSkyMixed = 1, kMixFitF64 = 2, kMixFitMixed = 3, kMixOps = 4 };
+constexpr int kMixKnots = 20;        // scale-length knots of the likelihood
+constexpr int kMixKnotsPass = 10;    // knots per pass of the mixed likelihood kernel
+
+struct MixArgs {
+  int64_t iters;
+  int n_items;                       // sources (sky model) or cells (likelihood) per iteration
+  const rlf::SrcModel *src;
+  const rlf::SrcMixed *src32;
+  const double4 *c64;
+  const float4 *c32;
+  const double *sk;                  // kMixKnots knot scales, twice
+  double *sink;
+  uint64_t *clk;
+  int64_t spin_ticks;                // the clock wave's window, fixed-clock ticks (10 ns)
+};
+
+// One lane's work: a visibility (ops 0-1) or an ellipticity grid point
+// (ops 2-3) taken through `iters` passes of the kernel's own inner loop.
+template <int OP>
+__device__ __forceinline__ double mix_work(const MixArgs &a, int t, const double2 *tab) {
+  double out = 0.0;
+  if (OP == kMixSkyF64 || OP == kMixSkyMixed) {
+    const double u = 1000.0 + 37.0 * (t & 4095), v = -2000.0 + 53.0 * (t >> 12), w = 11.0 * (t & 63);
+    double ar = 0.0, ai = 0.0;
+#pragma unroll 1
+    for (int64_t it = 0; it < a.iters; ++it) {
+      const double ui = u + (double)it;        // a new visibility each pass: nothing is loop-invariant
+      if (OP == kMixSkyF64) {
+        const double2 z = rlf::sum_f64(ui, v, w, a.src, 0, a.n_items, tab);
+        ar += z.x;
+        ai += z.y;
+      } else {
+        const float2 z = rlf::sum_mixed(ui, v, w, a.src32, 0, a.n_items);
+        ar += z.x;
+        ai += z.y;
+      }
+    }
+    out = ar + ai;
+  } else {
+    const double e1 = 0.02 * ((t % 81) - 40) * 0.9, e2 = 0.02 * (((t / 81) % 81) - 40) * 0.9;
+    const double det = 1.0 - e1 * e1 - e2 * e2;
+#pragma unroll 1
+    for (int64_t it = 0; it < a.iters; ++it) {
+      const double de = 1e-12 * (double)it;    // a new point each pass
+      // the knot scales are loaded per pass, wave-uniform, as the kernel
+      // loads them (the alternating copy keeps them from being hoisted out
+      // of the loop)
+      const double *skp = a.sk + (it & 1) * kMixKnots;
+      if (OP == kMixFitF64) {
+        double D[kMixKnots], M[kMixKnots], sk[kMixKnots];
+#pragma unroll
+        for (int k = 0; k < kMixKnots; ++k) {
+          D[k] = M[k] = 0.0;
+          sk[k] = skp[k];
+        }
+        const double id = 1.0 / det;
+        rlf::cell_sums_f64<kMixKnots>(a.c64, 0, a.n_items, (1.0 + e1 + de) * id, e2 * id, (1.0 - e1) * id, sk,
+                                      kMixKnots, D, M);
+#pragma unroll
+        for (int k = 0; k < kMixKnots; ++k) out += D[k] + M[k];
+      } else {
+        const double g = 1.0 / (det * det);
+#pragma unroll 1
+        for (int k0 = 0; k0 < kMixKnots; k0 += kMixKnotsPass) {
+          double D[kMixKnotsPass], M[kMixKnotsPass];
+          float sk[kMixKnotsPass];
+#pragma unroll
+          for (int k = 0; k < kMixKnotsPass; ++k) {
+            D[k] = M[k] = 0.0;
+            sk[k] = (float)(skp[k0 + k] * g);
+          }
+          rlf::cell_sums_f32<kMixKnotsPass>(a.c32, 0, a.n_items, (float)(1.0 + e1 + de), (float)e2,
+                                            (float)(1.0 - e1), sk, kMixKnotsPass, D, M);
+#pragma unroll
+          for (int k = 0; k < kMixKnotsPass; ++k) out += D[k] + M[k];
+        }
+      }
+    }
+  }
+  return out;
+}
+
+// Shader-clock and fixed 100 MHz counters (inline asm that touches no
+// memory; the wait for the result is in the same asm block).
+__device__ __forceinline__ uint64_t shader_clock() {
+  uint64_t c;
+  asm volatile("s_memtime %0\n\ts_waitcnt lgkmcnt(0)" : "=s"(c));
+  return c;
+}
+__device__ __forceinline__ uint64_t fixed_clock() {
+  uint64_t c;
+  asm volatile("s_memrealtime %0\n\ts_waitcnt lgkmcnt(0)" : "=s"(c));
+  return c;
+}
+
+// Wave 0 of block 0 is the clock: it reads both counters, sleeps until
+// spin_ticks of the fixed clock have passed (the caller sets that below
+// the run's duration, so the window lies inside the loaded run) and reads
+// them again; it does none of the work.  Every other wave runs the work.
+// (A clock read on the working waves' path would make the compiler take
+// the loop's loads as possibly clobbered and issue vector loads in place of
+// the kernels' scalar loads.)
+template <int OP>
+__global__ __launch_bounds__(256) void k_mix(MixArgs a) {
+  __shared__ double2 tab[rlf::kCisTable];
+  if (OP == kMixSkyF64) {
+    rlf::cis_table_init(tab);
+    __syncthreads();
+  }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    if (threadIdx.x == 0) {
+      const uint64_t c0 = shader_clock(), r0 = fixed_clock();
+      uint64_t r1 = r0;
+      while (r1 - r0 < (uint64_t)a.spin_ticks) {
+        __builtin_amdgcn_s_sleep(64);
+        r1 = fixed_clock();
+      }
+      a.clk[0] = shader_clock() - c0;
+      a.clk[1] = r1 - r0;
+    }
+    return;
+  }
+  a.sink[t] = mix_work<OP>(a, t, tab);
+}
+
+hipError_t launch_mix(int op, int blocks, const MixArgs &a, hipStream_t st) {
+  switch (op) {
+    case kMixSkyF64: hipLaunchKernelGGL(k_mix<kMixSkyF64>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kMixSkyMixed: hipLaunchKernelGGL(k_mix<kMixSkyMixed>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kMixFitF64: hipLaunchKernelGGL(k_mix<kMixFitF64>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kMixFitMixed: hipLaunchKernelGGL(k_mix<kMixFitMixed>, dim3(blocks), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" {
 
 // Number of probe kernels.
@@ -167,6 +323,112 @@ int valu_probe_run(int op, int blocks, int64_t iters, int reps, double *best_ms,
   if (clk) (void)hipFree(clk);
   *best_ms = best;
   *clock_hz = hz;
+  return (int)e;
+}
+
+// Number of kernel-mix probes (0: sky-model term FP64, 1: mixed; 2:
+// likelihood cell sums FP64, 20 knots in one pass; 3: mixed, two passes of
+// 10 knots over 32-cell FP32 blocks).
+int mix_probe_count(void) { return kMixOps; }
+
+// Run kernel-mix probe `op` over `blocks` blocks of 256 threads, `iters`
+// passes over `n_items` synthetic sources (ops 0-1) or cells (ops 2-3),
+// `reps` times; *best_ms, *clock_hz as for valu_probe_run, *units the work
+// of one run in the kernels' units: (visibility, source) pairs, or
+// (cell, e point, knot) triples.  Returns 0, or the HIP error code.  The
+// device buffers are allocated and freed here.
+int mix_probe_run(int op, int blocks, int64_t iters, int n_items, int reps, double *best_ms, double *clock_hz,
+                  double *units) {
+  if (op < 0 || op >= kMixOps || blocks < 1 || iters < 1 || n_items < 1 || n_items > (1 << 16) || reps < 1 ||
+      !best_ms || !clock_hz || !units)
+    return (int)hipErrorInvalidValue;
+  std::vector<rlf::SrcModel> hs(n_items);
+  std::vector<rlf::SrcMixed> hm(n_items);
+  std::vector<double4> h64(n_items);
+  std::vector<float4> h32(n_items);
+  for (int i = 0; i < n_items; ++i) {
+    // sources over a 1-degree field, scale lengths ~1 arcsec; cells on a
+    // 17 x 17 patch of a 5,400-wavelength facet lattice
+    const double l = 8.7e-3 * ((i * 37) % 101 - 50) / 50.0, m = 8.7e-3 * ((i * 53) % 97 - 48) / 48.0;
+    const double q = 4e-10 * (1.0 + (i % 7) * 0.1);
+    hs[i] = rlf::SrcModel{l, m, -0.5 * (l * l + m * m), 1e-4, q, 0.2 * q, 1.1 * q, 1.8e-4};
+    hm[i] = rlf::SrcMixed{l, m, -0.5 * (l * l + m * m), 1e-4f, (float)q, (float)(0.2 * q), (float)(1.1 * q), 1.8e-4};
+    const double uc = 5400.0 * (i % 17 - 8), vc = 5400.0 * ((i / 17) % 17 - 8);
+    h64[i] = make_double4(uc, vc, 1.0 + 1e-3 * i, 1e-3 * (i % 13));
+    h32[i] = make_float4((float)uc, (float)vc, 1.0f + 1e-3f * i, 1e-3f * (i % 13));
+  }
+  double hsk[2 * kMixKnots];
+  for (int k = 0; k < kMixKnots; ++k) {
+    const double al = (0.3 + 3.2 * k * k / 361.0) * 4.8481368110953599e-6;
+    hsk[k] = hsk[kMixKnots + k] = 4.0 * 9.8696044010893586 * al * al;
+  }
+  MixArgs a{};
+  a.iters = iters;
+  a.n_items = n_items;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rlf::SrcModel *ds = nullptr;
+  rlf::SrcMixed *dm = nullptr;
+  double4 *d64 = nullptr;
+  float4 *d32 = nullptr;
+  double *dsk = nullptr, *sink = nullptr;
+  uint64_t *clk = nullptr;
+  hipError_t e = hipMalloc(&ds, sizeof(rlf::SrcModel) * n_items);
+  if (e == hipSuccess) e = hipMalloc(&dm, sizeof(rlf::SrcMixed) * n_items);
+  if (e == hipSuccess) e = hipMalloc(&d64, sizeof(double4) * n_items);
+  if (e == hipSuccess) e = hipMalloc(&d32, sizeof(float4) * n_items);
+  if (e == hipSuccess) e = hipMalloc(&dsk, sizeof hsk);
+  if (e == hipSuccess) e = hipMalloc(&sink, sizeof(double) * 256 * (size_t)blocks);
+  if (e == hipSuccess) e = hipMalloc(&clk, sizeof(uint64_t) * 2);
+  if (e == hipSuccess) e = hipMemcpy(ds, hs.data(), sizeof(rlf::SrcModel) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dm, hm.data(), sizeof(rlf::SrcMixed) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d64, h64.data(), sizeof(double4) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d32, h32.data(), sizeof(float4) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dsk, hsk, sizeof hsk, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreate(&st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  a.src = ds;
+  a.src32 = dm;
+  a.c64 = d64;
+  a.c32 = d32;
+  a.sk = dsk;
+  a.sink = sink;
+  a.clk = clk;
+  double best = 1e300, hz = 0.0;
+  a.spin_ticks = 0;
+  if (e == hipSuccess) e = launch_mix(op, blocks, a, st);      // first launch
+  // a second warm-up, timed: the clock window of the measured runs is 70 % of it
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = launch_mix(op, blocks, a, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float warm_ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&warm_ms, e0, e1);
+  a.spin_ticks = (int64_t)(0.7 * warm_ms * 1e5);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_mix(op, blocks, a, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    uint64_t c[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpy(c, clk, sizeof c, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      hz = c[1] ? (double)c[0] / ((double)c[1] * 1e-8) : 0.0;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  for (void *ptr : {(void *)ds, (void *)dm, (void *)d64, (void *)d32, (void *)dsk, (void *)sink, (void *)clk})
+    if (ptr) (void)hipFree(ptr);
+  *best_ms = best;
+  *clock_hz = hz;
+  const double threads = 256.0 * blocks - 64.0;       // the clock wave does no work
+  *units = threads * (double)iters * n_items * (op >= kMixFitF64 ? kMixKnots : 1);
   return (int)e;
 }
 

@@ -8,7 +8,7 @@ Training facets come from the SKA-MID-like field generator (config 1: its
 array, 8 h track, one channel at 1.4 GHz and noise level), each source
 isolated (the residual handed to the extraction is pure noise, so every
 facet holds its own exact model plus noise: the "single source" case of
-Sec. 4.2), a fresh noise realisation per batch of sources.  The source
+Sec. 4.1), a fresh noise realisation per batch of sources.  The source
 population is config 1's (50-200 uJy, log-normal sizes) or, with
 population="config3", that of the 10,000-source field (10-1000 uJy, sizes
 from the size-flux relation), so that the network sees the signal-to-noise

@@ -7,7 +7,7 @@ config's uv coverage:
   config 3:    10 uJy at the Eq. 4 median size, circular, SNR 8.5 (the
                paper's faintest SNR, Sec. 4.2);
   "kscan":     the facet-size experiment on the config-1 coverage: the same
-               10 uJy reference at SNR 19 (Sec. 4.2: the realistic noise
+               10 uJy reference at SNR 19 (Sec. 4.1: the realistic noise
                variance divided by 5, a minimum SNR of about 19).
 The model is evaluated with the oracle only.
 

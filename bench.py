@@ -474,6 +474,13 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def _sources_de_above(de, tol=1e-3):
+    """Sources whose estimate moved by more than tol in e1 or e2; de is the
+    e1 differences followed by the e2 differences of the same sources."""
+    m = de.size // 2
+    return int(np.count_nonzero(np.maximum(np.abs(de[:m]), np.abs(de[m:])) > tol))
+
+
 def _evaluated_points(win, stride):
     """Valid grid points inside each window plus the lattice points outside it."""
     i = np.arange(81)
@@ -519,6 +526,7 @@ def _narrowed_rows(ctx, net, f, cat, a, t_ext, t_full, nsigmas, check_stride, fu
                     "end_to_end_sources_per_s": round(n / ((t_ext + t_nar) * 1e-3), 1),
                     "fit_speedup_vs_plain": round(t_full / t_nar, 3),
                     "rms_de_vs_full": rms, "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                    "sources_abs_de_above_1e-3": _sources_de_above(de),
                     "within_1e-3": bool(rms <= 1e-3), "fallback_fraction": fb,
                     "mean_window_points": round(float(area.mean()), 1),
                     "full_grid_windows": int(np.count_nonzero(area == 81 * 81)),
@@ -668,6 +676,7 @@ def run_surrogate(steps, n_train, epochs, nsigmas, populations, check_stride, fu
                         "fit_speedup_vs_full_grid": round(t_full / t_lat, 3),
                         "rms_de_vs_full": float(np.sqrt(np.mean(de ** 2))),
                         "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                        "sources_abs_de_above_1e-3": _sources_de_above(de),
                         "fallback_fraction": float(np.mean((b["flags"] & rlf.RLF_FLAG_FALLBACK) > 0))})
         log(f"[bench] config 3: lattice-seeded fit, stride {stride}: {t_lat:.2f} ms; "
             f"RMS(de) {lattice[-1]['rms_de_vs_full']:.2e}; fallback {lattice[-1]['fallback_fraction']:.3f}")
@@ -876,6 +885,7 @@ def run_form(precision, steps, warmup, seq_chunks=(), pos_sigmas=(), pos_sides=(
                         "fit_speedup_vs_full_grid": round(float(stage_ms[2]) / lms, 3),
                         "step_sources_per_s": round(n / ((stage_ms[0] + stage_ms[1] + lms) * 1e-3), 1),
                         "rms_de_vs_full": float(np.sqrt(np.mean(de ** 2))), "max_abs_de_vs_full": float(np.max(np.abs(de))),
+                        "sources_abs_de_above_1e-3": _sources_de_above(de),
                         "fallback_fraction": float(np.mean((lfl & rlf.RLF_FLAG_FALLBACK) > 0))})
         log(f"[bench] {precision}: lattice-seeded fit, stride {stride}: {lms:.2f} ms (full grid {stage_ms[2]:.2f} ms); "
             f"RMS(de) {lattice[-1]['rms_de_vs_full']:.2e}; fallback {lattice[-1]['fallback_fraction']:.3f}")

@@ -123,9 +123,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // v_mfma_f32_32x32x16_bf16 tiles.  Both k tiles are staged [row][k] in LDS
 // (rows padded to 72 BF16, so the eight lanes of one 16-byte read phase hit
 // distinct banks) with 16-byte global loads and LDS stores; the LDS holds two
-// k tiles, and the global loads of tile t+1 are issued before the MFMAs of
-// tile t and stored to the other half after them, so one barrier per tile
-// separates the phases.  Rows beyond M or N and k beyond the slice read as
+// k tiles and the registers two more, so the global loads of a tile are
+// issued two tiles ahead of its MFMAs, and one barrier per tile separates
+// the phases.  Rows beyond M or N and k beyond the slice read as
 // zero (K a multiple of 8, lda and ldb multiples of 8).  grid.z splits K in
 // multiples of 64; with more than one slice each writes its partial product
 // to the workspace and k_reduce_split adds the slices in order.
@@ -155,56 +155,93 @@ __device__ __forceinline__ void nt_store(__bf16 *lds, const bf16x8 (&r)[4]) {
   }
 }
 
+// The MFMAs of one k tile from LDS into the wave's 2 x 2 accumulator tiles.
+__device__ __forceinline__ void nt_mfma(f32x16 (&acc)[2][2], const __bf16 *A, const __bf16 *B, int wm, int wn,
+                                        int lane) {
+#pragma unroll
+  for (int kk = 0; kk < kTK; kk += 16) {
+    bf16x8 fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      fa[i] = *reinterpret_cast<const bf16x8 *>(A + (wm + i * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      fb[j] = *reinterpret_cast<const bf16x8 *>(B + (wn + j * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// XCD-aware tile order.  Blocks go to the eight XCDs round-robin by linear
+// block index; the tile a block computes is chosen so that each XCD takes a
+// contiguous run of tiles in (n tile, m tile, k slice) order, i.e. all the
+// n tiles of an m tile (which read the same rows of A) share one XCD's L2.
+// Without it the four n tiles of a 512-wide product sat on four XCDs and
+// each fetched the same A panel.
+__device__ __forceinline__ void nt_tile(int &nt, int &mt, int &z) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int n = gx * gy * (int)gridDim.z;
+  const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int x = L & 7, r = L >> 3, q = n >> 3, rem = n & 7;
+  const int T = x * q + min(x, rem) + r;
+  nt = T % gx;
+  mt = (T / gx) % gy;
+  z = T / (gx * gy);
+}
+
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmNTArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 sa[2][kTM * kLdT];
   __shared__ __attribute__((aligned(16))) __bf16 sb[2][kTN * kLdT];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  int nt, mt, z;
+  nt_tile(nt, mt, z);
+  const int m0 = mt * kTM, n0 = nt * kTN;
   const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
   const int kper = ((g.K + (int)gridDim.z - 1) / (int)gridDim.z + kTK - 1) / kTK * kTK;
-  const int kb = blockIdx.z * kper, ke = min(g.K, kb + kper);
+  const int kb = z * kper, ke = min(g.K, kb + kper);
+  const int T = kb < ke ? (ke - kb + kTK - 1) / kTK : 0;      // k tiles of this slice
   f32x16 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-  bf16x8 ra[4], rb[4];
-  int buf = 0;
-  if (kb < ke) {
-    nt_load(ra, g.a, g.lda, m0, g.M, kb, ke);
-    nt_load(rb, g.b, g.ldb, n0, g.N, kb, ke);
-    nt_store(sa[0], ra);
-    nt_store(sb[0], rb);
+  // Two register stages: at the start of step t, LDS half t % 2 holds tile t,
+  // stage (t + 1) % 2 tile t + 1 and stage t % 2 tile t + 2 (loads in
+  // flight).  After the MFMAs of tile t, tile t + 1 goes to the other LDS
+  // half and its stage is reloaded with tile t + 3, so a tile's global loads
+  // have two steps of MFMAs to arrive.
+  bf16x8 ra0[4], rb0[4], ra1[4], rb1[4];
+  auto load = [&](bf16x8 (&ra)[4], bf16x8 (&rb)[4], int t) {
+    nt_load(ra, g.a, g.lda, m0, g.M, kb + t * kTK, ke);
+    nt_load(rb, g.b, g.ldb, n0, g.N, kb + t * kTK, ke);
+  };
+  if (T > 0) {
+    load(ra0, rb0, 0);
+    nt_store(sa[0], ra0);
+    nt_store(sb[0], rb0);
   }
+  if (T > 1) load(ra1, rb1, 1);
+  if (T > 2) load(ra0, rb0, 2);
   __syncthreads();
-  for (int k0 = kb; k0 < ke; k0 += kTK) {
-    const bool more = k0 + kTK < ke;
-    if (more) {
-      nt_load(ra, g.a, g.lda, m0, g.M, k0 + kTK, ke);
-      nt_load(rb, g.b, g.ldb, n0, g.N, k0 + kTK, ke);
-    }
-    const __bf16 *A = sa[buf], *B = sb[buf];
-#pragma unroll
-    for (int kk = 0; kk < kTK; kk += 16) {
-      bf16x8 fa[2], fb[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        fa[i] = *reinterpret_cast<const bf16x8 *>(A + (wm + i * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        fb[j] = *reinterpret_cast<const bf16x8 *>(B + (wn + j * 32 + (lane & 31)) * kLdT + kk + 8 * (lane >> 5));
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-    }
-    if (more) {
-      nt_store(sa[buf ^ 1], ra);
-      nt_store(sb[buf ^ 1], rb);
+  for (int t = 0; t < T; t += 2) {
+    nt_mfma(acc, sa[0], sb[0], wm, wn, lane);
+    if (t + 1 < T) {
+      nt_store(sa[1], ra1);
+      nt_store(sb[1], rb1);
+      if (t + 3 < T) load(ra1, rb1, t + 3);
     }
     __syncthreads();
-    buf ^= 1;
+    if (t + 1 >= T) break;
+    nt_mfma(acc, sa[1], sb[1], wm, wn, lane);
+    if (t + 2 < T) {
+      nt_store(sa[0], ra0);
+      nt_store(sb[0], rb0);
+      if (t + 4 < T) load(ra0, rb0, t + 4);
+    }
+    __syncthreads();
   }
-  float *outp = gridDim.z > 1 ? g.ws + (int64_t)blockIdx.z * g.M * g.N : g.c;
+  float *outp = gridDim.z > 1 ? g.ws + (int64_t)z * g.M * g.N : g.c;
   const int64_t ld = gridDim.z > 1 ? g.N : g.ldc;
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)

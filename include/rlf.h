@@ -444,6 +444,17 @@ int rlf_mlp_forward(rlf_mlp *net, const void *x, int64_t rows, float *y);
  * batch loss is written to device *loss (FP64). */
 int rlf_mlp_train_step(rlf_mlp *net, const void *x, const float *target, int64_t rows, float lr, double *loss);
 
+/* The network on a facet object directly: the inputs of its sources (as
+ * rlf_mlp_features forms them) go through the network's own staging buffer
+ * in chunks of max_batch, and y (device FP32 [n_src x 6]) receives what
+ * rlf_mlp_forward would give for them, bit for bit.  The facet object must
+ * belong to the network's context. */
+int rlf_mlp_predict(rlf_mlp *net, const rlf_facets *facets, float *y);
+
+/* One Adam step on the sources of a facet object (1 <= n_src <= max_batch),
+ * their inputs formed as by rlf_mlp_features; otherwise rlf_mlp_train_step. */
+int rlf_mlp_train_facets(rlf_mlp *net, const rlf_facets *facets, const float *target, float lr, double *loss);
+
 /* Training targets around the method's own fits (the network then learns the
  * posterior mean as its mean and, through the NLL, the posterior width plus
  * its own error as its variance): for each of `rows` sources, from its

@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *x, __bf16 *y, int6
 // Network input: facet cells inside -32..31 on both axes, Vbar / (S g), g the
 // observation's mean spectral factor, clipped to +-kFeatureClip.
 __global__ __launch_bounds__(256) void k_features(FeatureArgs a) {
-  const int s = blockIdx.x;
-  __bf16 *x = a.x + (int64_t)s * 8192;
+  const int s = a.s0 + (int)blockIdx.x;
+  __bf16 *x = a.x + (int64_t)blockIdx.x * 8192;
   for (int i = threadIdx.x; i < 8192; i += blockDim.x) x[i] = to_bf16(0.0f);
   __syncthreads();
   const double inv = 1.0 / (a.src[s].flux * a.spec_norm);

@@ -287,13 +287,14 @@ struct GemmNTArgs {
 };
 
 struct FeatureArgs {
-  int32_t n_src;
+  int32_t s0;                // first source of the rows written
+  int32_t n_src;             // rows written (sources s0 .. s0 + n_src - 1)
   const int64_t *offsets;
   const int32_t *ix, *iy;
   const double *vre, *vim;
   const SrcModel *src;
   double spec_norm;          // mean over channels of (nu_c / nu_ref)^beta
-  __bf16 *x;                 // [n_src * 8192]
+  __bf16 *x;                 // [n_src * 8192], row r for source s0 + r
 };
 
 // Launchers (enqueue on `st`; return the launch status).

@@ -43,6 +43,7 @@ struct rlf_mlp {
   // input and the gradient dZ transposed ([in x rows], [512 x rows])
   __bf16 *wbt = nullptr;
   __bf16 *xt = nullptr, *ht = nullptr, *dzt = nullptr;
+  __bf16 *xf = nullptr;                      // network inputs of a facet object's sources [max_batch x 8192]
 };
 
 namespace {
@@ -74,6 +75,7 @@ void mlp_release(rlf_mlp *n) {
   dfree(n->xt);
   dfree(n->ht);
   dfree(n->dzt);
+  dfree(n->xf);
 }
 
 constexpr int kMaxSplitBlocks = 512;                  // tiles x K slices
@@ -218,6 +220,7 @@ int rlf_mlp_create(rlf_ctx *c, int64_t max_batch, rlf_mlp **out) {
     if ((rc = dalloc(c, &n->xt, B * kIn))) break;
     if ((rc = dalloc(c, &n->ht, B * kHid))) break;
     if ((rc = dalloc(c, &n->dzt, B * kHid))) break;
+    if ((rc = dalloc(c, &n->xf, B * kIn))) break;
     hipError_t e = hipMemset(n->w, 0, sizeof(float) * kParams);
     if (e == hipSuccess) e = hipMemset(n->m, 0, sizeof(float) * kParams);
     if (e == hipSuccess) e = hipMemset(n->v, 0, sizeof(float) * kParams);
@@ -372,12 +375,13 @@ int rlf_mlp_load(rlf_mlp *n, const char *path) {
   return rlf_mlp_set_state(n, buf.data(), buf.data() + kParams, buf.data() + 2 * kParams, h.step);
 }
 
-int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {
-  if (!c) return RLF_EINVAL;
-  if (!f || f->ctx != c || !x) return fail(c, RLF_EINVAL, "rlf_mlp_features: arguments");
-  HIPCHK(c, hipSetDevice(c->device));
+namespace {
+
+// Network inputs of sources [s0, s0 + count) of facet object f into x.
+hipError_t facet_features(const rlf_facets *f, int64_t s0, int64_t count, __bf16 *x, hipStream_t st) {
   FeatureArgs a{};
-  a.n_src = (int32_t)f->n_src;
+  a.s0 = (int32_t)s0;
+  a.n_src = (int32_t)count;
   a.offsets = f->cells.offsets;
   a.ix = f->cells.ix;
   a.iy = f->cells.iy;
@@ -385,9 +389,42 @@ int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {
   a.vim = f->cells.vim;
   a.src = f->d_src;
   a.spec_norm = f->spec_norm;
-  a.x = reinterpret_cast<__bf16 *>(x);
-  HIPCHK(c, launch_features(a, c->stream));
+  a.x = x;
+  return launch_features(a, st);
+}
+
+}  // namespace
+
+int rlf_mlp_features(rlf_ctx *c, const rlf_facets *f, void *x) {
+  if (!c) return RLF_EINVAL;
+  if (!f || f->ctx != c || !x) return fail(c, RLF_EINVAL, "rlf_mlp_features: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (f->n_src == 0) return RLF_OK;
+  HIPCHK(c, facet_features(f, 0, f->n_src, reinterpret_cast<__bf16 *>(x), c->stream));
   return RLF_OK;
+}
+
+int rlf_mlp_predict(rlf_mlp *n, const rlf_facets *f, float *y) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  if (!f || f->ctx != c || !y) return fail(c, RLF_EINVAL, "rlf_mlp_predict: arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  for (int64_t s0 = 0; s0 < f->n_src; s0 += n->max_batch) {
+    const int nb = (int)std::min<int64_t>(n->max_batch, f->n_src - s0);
+    HIPCHK(c, facet_features(f, s0, nb, n->xf, c->stream));
+    if (int e = forward_chunk(n, n->xf, nb, y + s0 * kOut)) return e;
+  }
+  return RLF_OK;
+}
+
+int rlf_mlp_train_facets(rlf_mlp *n, const rlf_facets *f, const float *target, float lr, double *loss) {
+  if (!n) return RLF_EINVAL;
+  rlf_ctx *c = n->c;
+  if (!f || f->ctx != c || !target || !loss || f->n_src < 1 || f->n_src > n->max_batch)
+    return fail(c, RLF_EINVAL, "rlf_mlp_train_facets: arguments (1 <= n_src <= max_batch)");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, facet_features(f, 0, f->n_src, n->xf, c->stream));
+  return rlf_mlp_train_step(n, n->xf, target, f->n_src, lr, loss);
 }
 
 int rlf_mlp_forward(rlf_mlp *n, const void *x, int64_t rows, float *y) {

@@ -99,6 +99,8 @@ _SIGNATURES = {
     "rlf_mlp_features": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
     "rlf_mlp_forward": ([_c_vp, _c_vp, ctypes.c_int64, _c_vp], ctypes.c_int),
     "rlf_mlp_train_step": ([_c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_float, _c_vp], ctypes.c_int),
+    "rlf_mlp_predict": ([_c_vp, _c_vp, _c_vp], ctypes.c_int),
+    "rlf_mlp_train_facets": ([_c_vp, _c_vp, _c_vp, ctypes.c_float, _c_vp], ctypes.c_int),
     "rlf_mlp_posterior_targets": ([_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_uint64, _c_vp], ctypes.c_int),
     "rlf_mlp_windows": ([_c_vp, _c_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _c_vp],
@@ -437,6 +439,14 @@ class Mlp:
     def train_step(self, x, target, lr, loss):
         return self.ctx._check(lib().rlf_mlp_train_step(self.h, _ptr(x), _ptr(target), int(x.shape[0]),
                                                         float(lr), _ptr(loss)))
+
+    def predict(self, facets: "Facets", y):
+        """rlf_mlp_predict: the network on every source of a facet object."""
+        return self.ctx._check(lib().rlf_mlp_predict(self.h, facets.h, _ptr(y)))
+
+    def train_facets(self, facets: "Facets", target, lr, loss):
+        """rlf_mlp_train_facets: one Adam step on the sources of a facet object."""
+        return self.ctx._check(lib().rlf_mlp_train_facets(self.h, facets.h, _ptr(target), float(lr), _ptr(loss)))
 
     def posterior_targets(self, e1, e2, s1, s2, ln_alpha, target, kappa, seed):
         """rlf_mlp_posterior_targets: targets drawn around the full-grid estimates."""

@@ -152,6 +152,58 @@ def test_features_match_oracle_facets(ctx, freq):
     f.free()
 
 
+def test_predict_and_train_on_facet_objects(ctx):
+    """rlf_mlp_predict equals features + forward bit for bit, across chunks
+    of max_batch with a ragged last chunk (10 sources, max_batch 4), and
+    rlf_mlp_train_facets equals train_step on the same features (parameters,
+    Adam state and loss bit for bit); a facet object larger than max_batch
+    is refused for training."""
+    from paper_2203_14071_amd import surrogate
+    torch = G.torch_cuda()
+    cfg = synth.CONFIGS[0]
+    o = synth.observation(0, cfg)
+    cat = synth.catalogue(cfg, synth.rng(0, synth.STREAM_CAT))
+    nz = synth.noise(cfg, synth.rng(0, synth.STREAM_NOISE), o.n_rows * o.n_chan)
+    obs = G.make_obs(o, nz)
+    f = ctx.facets_create(obs, cat)
+    ctx.extract_facets(obs, cat, obs.vis, f)
+    n = cat.n_src
+    assert n == 10
+    init = surrogate.init_params(out_scale=0.1)
+    x = torch.empty((n, M.N_IN), dtype=torch.bfloat16, device="cuda:0")
+    small = rlf.Mlp(ctx, max_batch=4)
+    small.set_state(init)
+    small.features(f, x)
+    y_ref = torch.empty((n, 6), dtype=torch.float32, device="cuda:0")
+    y = torch.full((n, 6), float("nan"), dtype=torch.float32, device="cuda:0")
+    small.forward(x, y_ref)
+    small.predict(f, y)
+    ctx.sync()
+    assert torch.equal(y, y_ref)
+    rng = np.random.default_rng(4)
+    tgt = torch.from_numpy(rng.standard_normal((n, 3)).astype(np.float32) * 0.3).to("cuda:0")
+    with pytest.raises(rlf.RlfError):
+        small.train_facets(f, tgt, 1e-3, torch.zeros(1, dtype=torch.float64, device="cuda:0"))
+    a, b = rlf.Mlp(ctx, max_batch=16), rlf.Mlp(ctx, max_batch=16)
+    a.set_state(init)
+    b.set_state(init)
+    la = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    lb = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        a.train_step(x, tgt, 1e-3, la)
+        b.train_facets(f, tgt, 1e-3, lb)
+    ctx.sync()
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("params", "m", "v"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sa["step"] == sb["step"] == 2
+    assert la.item() == lb.item()
+    assert not np.array_equal(sa["params"], np.asarray(init, dtype=np.float32))
+    for net in (small, a, b):
+        net.free()
+    f.free()
+
+
 def test_training_reduces_loss_and_resumes_bit_exactly(ctx):
     torch = G.torch_cuda()
     rng = np.random.default_rng(12)

@@ -252,14 +252,30 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmNTArgs g) {
       }
 }
 
-// dst[c][r] = src[r][c] for a BF16 matrix [rows x cols]: 64 x 64 tiles
+// dst[c][r] = src[r][c] for BF16 matrices [rows x cols]: 64 x 64 tiles
 // through LDS, four BF16 (8 bytes) per global access when the tile is whole
-// and the row lengths are multiples of 4, else one element per access.
-__global__ __launch_bounds__(256) void k_transpose_bf16(const __bf16 *__restrict__ src, int64_t rows, int64_t cols,
-                                                        __bf16 *__restrict__ dst) {
+// and the row lengths are multiples of 4, else one element per access.  One
+// launch serves several matrices: the blocks run over the tiles of job 0,
+// then job 1, ...
+struct TransposeBatch {
+  int n;
+  TransposeJob job[kMaxTransposeJobs];
+  int64_t first_tile[kMaxTransposeJobs + 1];   // prefix sums of the jobs' tile counts
+  int64_t tiles_x[kMaxTransposeJobs];          // tiles along a job's columns
+};
+
+__global__ __launch_bounds__(256) void k_transpose_bf16(TransposeBatch tb) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   __shared__ __bf16 t[64][66];
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int64_t b = blockIdx.x;
+  int jn = 0;
+  while (jn + 1 < tb.n && b >= tb.first_tile[jn + 1]) ++jn;
+  const TransposeJob &J = tb.job[jn];
+  const __bf16 *__restrict__ src = J.src;
+  __bf16 *__restrict__ dst = J.dst;
+  const int64_t rows = J.rows, cols = J.cols;
+  const int64_t local = b - tb.first_tile[jn];
+  const int64_t r0 = (local / tb.tiles_x[jn]) * 64, c0 = (local % tb.tiles_x[jn]) * 64;
   const bool whole = r0 + 64 <= rows && c0 + 64 <= cols && (cols % 4) == 0 && (rows % 4) == 0 &&
                      ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7) == 0;
   if (whole) {
@@ -540,9 +556,19 @@ hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_transpose_bf16(const __bf16 *src, int64_t rows, int64_t cols, __bf16 *dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64)), dim3(256), 0,
-                     st, src, rows, cols, dst);
+hipError_t launch_transpose_bf16(const TransposeJob *jobs, int n_jobs, hipStream_t st) {
+  if (n_jobs < 1 || n_jobs > kMaxTransposeJobs) return hipErrorInvalidValue;
+  TransposeBatch tb{};
+  tb.n = n_jobs;
+  tb.first_tile[0] = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (jobs[j].rows < 1 || jobs[j].cols < 1) return hipErrorInvalidValue;
+    tb.job[j] = jobs[j];
+    tb.tiles_x[j] = (jobs[j].cols + 63) / 64;
+    tb.first_tile[j + 1] = tb.first_tile[j] + tb.tiles_x[j] * ((jobs[j].rows + 63) / 64);
+  }
+  for (int j = n_jobs; j < kMaxTransposeJobs; ++j) tb.first_tile[j + 1] = tb.first_tile[n_jobs];
+  hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)tb.first_tile[n_jobs]), dim3(256), 0, st, tb);
   return hipGetLastError();
 }
 

@@ -335,7 +335,15 @@ hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *d
 hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
                          hipStream_t st);
 hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st);
-hipError_t launch_transpose_bf16(const __bf16 *src, int64_t rows, int64_t cols, __bf16 *dst, hipStream_t st);
+// dst[c][r] = src[r][c] for up to kMaxTransposeJobs BF16 matrices
+// [rows x cols] in one launch.
+constexpr int kMaxTransposeJobs = 4;
+struct TransposeJob {
+  const __bf16 *src;
+  int64_t rows, cols;
+  __bf16 *dst;
+};
+hipError_t launch_transpose_bf16(const TransposeJob *jobs, int n_jobs, hipStream_t st);
 hipError_t launch_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n, float lr, int64_t step,
                        hipStream_t st);
 hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);

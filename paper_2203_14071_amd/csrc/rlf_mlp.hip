@@ -154,10 +154,10 @@ int gemm_nt(rlf_mlp *net, const __bf16 *a, int64_t lda, const __bf16 *b, int64_t
 int update_wbt(rlf_mlp *n) {
   const int64_t offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
   const int64_t din[4] = {kIn, kHid, kHid, kHid}, dout[4] = {kHid, kHid, kHid, kOut};
-  for (int l = 0; l < 4; ++l) {
-    hipError_t e = launch_transpose_bf16(n->wb + offW[l], din[l], dout[l], n->wbt + offW[l], n->c->stream);
-    if (e != hipSuccess) return hip_fail(n->c, e, "weight transpose launch");
-  }
+  TransposeJob jobs[4];
+  for (int l = 0; l < 4; ++l) jobs[l] = TransposeJob{n->wb + offW[l], din[l], dout[l], n->wbt + offW[l]};
+  hipError_t e = launch_transpose_bf16(jobs, 4, n->c->stream);
+  if (e != hipSuccess) return hip_fail(n->c, e, "weight transpose launch");
   return RLF_OK;
 }
 
@@ -466,8 +466,8 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
     if (nt_rows) {
       // dW = h^T dZ with both operands transposed to [features x rows]
       __bf16 *hin_t = l == 0 ? n->xt : n->ht;
-      HIPCHK(c, launch_transpose_bf16(hin, nb, kin, hin_t, c->stream));
-      HIPCHK(c, launch_transpose_bf16(n->dzb, nb, kHid, n->dzt, c->stream));
+      const TransposeJob jobs[2] = {{hin, nb, kin, hin_t}, {n->dzb, nb, kHid, n->dzt}};
+      HIPCHK(c, launch_transpose_bf16(jobs, 2, c->stream));
       if (int e = gemm_nt(n, hin_t, nb, n->dzt, nb, n->g + offW[l], kHid, kin, kHid, nb)) return e;
     } else {
       if (int e = gemm(n, hin, 1, kin, n->dzb, kHid, 1, n->g + offW[l], kin, kHid, nb)) return e;

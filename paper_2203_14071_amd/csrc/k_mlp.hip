@@ -393,14 +393,29 @@ __global__ __launch_bounds__(256) void k_head(const float *y, const float *t, in
   if (threadIdx.x == 0) unsafeAtomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n);
 }
 
-// dz = dh * GELU'(z): FP32 (for the bias) and BF16 (for the products)
-__global__ __launch_bounds__(256) void k_gelu_back(const float *dh, const float *z, int64_t n, float *dz,
-                                                   __bf16 *dzb) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float v = dh[i] * gelu_grad(z[i]);
-    dz[i] = v;
-    dzb[i] = to_bf16(v);
-  }
+// The hidden layers' backward epilogue and their bias gradients' first step
+// in one pass: dZ = dH gelu'(Z) (BF16 copy for the products) over a block
+// of 64 columns and a slice of rows, with the slice's column sums formed as
+// k_colsum_part forms them (four row groups, added in order) into
+// part[y][col]; k_colsum_join then adds the slices.
+__global__ __launch_bounds__(256) void k_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols,
+                                                          int64_t per, __bf16 *dzb, float *part) {
+  __shared__ float sh[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
+  float acc = 0.0f;
+  if (col < cols)
+    for (int64_t r = r0 + rg; r < r1; r += 4) {
+      const int64_t i = r * cols + col;
+      const float v = dh[i] * gelu_grad(z[i]);
+      dzb[i] = to_bf16(v);
+      acc += v;
+    }
+  sh[rg][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (rg == 0 && col < cols)
+    part[(int64_t)blockIdx.y * cols + col] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_adam(float *w, __bf16 *wb, const float *g, float *m, float *v, int64_t n,
@@ -529,18 +544,31 @@ hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __b
   return hipGetLastError();
 }
 
-hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *dz, __bf16 *dzb, hipStream_t st) {
-  hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(n)), dim3(256), 0, st, dh, z, n, dz, dzb);
-  return hipGetLastError();
+// Row slices of the two-step column sums: at least 32 rows, at most 256
+// slices (one block per slice and 64 columns), within the workspace.
+void colsum_slices(int64_t rows, int cols, int64_t ws_floats, int64_t *per, int *nsl) {
+  const int64_t slices = std::max<int64_t>(1, std::min<int64_t>({256, (rows + 31) / 32, ws_floats / std::max(1, cols)}));
+  *per = (rows + slices - 1) / slices;
+  *nsl = (int)((rows + *per - 1) / *per);
 }
 
 hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
                          hipStream_t st) {
-  // slices of at least 32 rows, at most 256 of them (one block per slice and 64 columns)
-  const int64_t slices = std::max<int64_t>(1, std::min<int64_t>({256, (rows + 31) / 32, ws_floats / std::max(1, cols)}));
-  const int64_t per = (rows + slices - 1) / slices;
-  const int nsl = (int)((rows + per - 1) / per);
+  int64_t per;
+  int nsl;
+  colsum_slices(rows, cols, ws_floats, &per, &nsl);
   hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nsl), dim3(256), 0, st, d, rows, cols, per, ws);
+  hipLaunchKernelGGL(k_colsum_join, dim3((cols + 3) / 4), dim3(256), 0, st, ws, nsl, cols, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols, __bf16 *dzb, float *db,
+                                   float *ws, int64_t ws_floats, hipStream_t st) {
+  int64_t per;
+  int nsl;
+  colsum_slices(rows, cols, ws_floats, &per, &nsl);
+  hipLaunchKernelGGL(k_gelu_back_colsum, dim3((cols + 63) / 64, nsl), dim3(256), 0, st, dh, z, rows, cols, per, dzb,
+                     ws);
   hipLaunchKernelGGL(k_colsum_join, dim3((cols + 3) / 4), dim3(256), 0, st, ws, nsl, cols, db);
   return hipGetLastError();
 }

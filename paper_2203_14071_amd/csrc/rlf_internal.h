@@ -331,7 +331,10 @@ hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int col
                            hipStream_t st);
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st);
-hipError_t launch_gelu_back(const float *dh, const float *z, int64_t n, float *dz, __bf16 *dzb, hipStream_t st);
+// dZ = dH gelu'(Z) as BF16 [rows x cols] and db = column sums of dZ (FP32,
+// summed as launch_colsum sums), ws holding the row slices' partial sums.
+hipError_t launch_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols, __bf16 *dzb, float *db,
+                                   float *ws, int64_t ws_floats, hipStream_t st);
 hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
                          hipStream_t st);
 hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st);

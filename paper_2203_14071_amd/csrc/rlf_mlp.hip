@@ -35,7 +35,7 @@ struct rlf_mlp {
   __bf16 *wb = nullptr;
   float *z[3] = {nullptr, nullptr, nullptr};
   __bf16 *h[3] = {nullptr, nullptr, nullptr};
-  float *y = nullptr, *cbuf = nullptr, *dy = nullptr, *dh = nullptr, *dz = nullptr;
+  float *y = nullptr, *cbuf = nullptr, *dy = nullptr, *dh = nullptr;
   float *ws = nullptr;                       // split-K partial products, column-sum slices
   __bf16 *dyb = nullptr, *dzb = nullptr;
   // k-contiguous operands of the NT GEMM: the BF16 weights transposed per
@@ -67,7 +67,6 @@ void mlp_release(rlf_mlp *n) {
   dfree(n->cbuf);
   dfree(n->dy);
   dfree(n->dh);
-  dfree(n->dz);
   dfree(n->dyb);
   dfree(n->dzb);
   dfree(n->ws);
@@ -213,7 +212,6 @@ int rlf_mlp_create(rlf_ctx *c, int64_t max_batch, rlf_mlp **out) {
     if ((rc = dalloc(c, &n->dy, B * kOut))) break;
     if ((rc = dalloc(c, &n->dyb, B * kOut))) break;
     if ((rc = dalloc(c, &n->dh, B * kHid))) break;
-    if ((rc = dalloc(c, &n->dz, B * kHid))) break;
     if ((rc = dalloc(c, &n->dzb, B * kHid))) break;
     if ((rc = dalloc(c, &n->ws, kWsFloats))) break;
     if ((rc = dalloc(c, &n->wbt, kParams))) break;
@@ -459,8 +457,8 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   // the NT GEMM needs the batch dimension in multiples of 8 for the weight gradients
   const bool nt_rows = nb % 8 == 0;
   for (int l = 2; l >= 0; --l) {
-    HIPCHK(c, launch_gelu_back(n->dh, n->z[l], (int64_t)nb * kHid, n->dz, n->dzb, c->stream));
-    HIPCHK(c, launch_colsum(n->dz, nb, kHid, n->g + offB[l], n->ws, kWsFloats, c->stream));
+    HIPCHK(c, launch_gelu_back_colsum(n->dh, n->z[l], nb, kHid, n->dzb, n->g + offB[l], n->ws, kWsFloats,
+                                      c->stream));
     const __bf16 *hin = l == 0 ? xb : n->h[l - 1];
     const int kin = l == 0 ? kIn : kHid;
     if (nt_rows) {

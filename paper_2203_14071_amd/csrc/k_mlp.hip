@@ -306,24 +306,6 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(TransposeBatch tb) {
   }
 }
 
-// Column sums in two deterministic steps: block (x, y) sums its slice of rows
-// for 64 columns (four row groups, added in order) into part[y][col]; then
-// each column adds the slices in order.
-__global__ __launch_bounds__(256) void k_colsum_part(const float *d, int64_t rows, int cols, int64_t per,
-                                                     float *part) {
-  __shared__ float sh[4][64];
-  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int rg = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
-  float acc = 0.0f;
-  if (col < cols)
-    for (int64_t r = r0 + rg; r < r1; r += 4) acc += d[r * cols + col];
-  sh[rg][threadIdx.x & 63] = acc;
-  __syncthreads();
-  if (rg == 0 && col < cols)
-    part[(int64_t)blockIdx.y * cols + col] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
-}
-
 // One wave per column: lane j adds slices j, j + 64, ... in order, then the
 // lanes are added by a fixed butterfly (the same sum on every run).
 __global__ __launch_bounds__(256) void k_colsum_join(const float *part, int slices, int cols, float *db) {
@@ -365,6 +347,85 @@ __global__ __launch_bounds__(256) void k_bias_act(const float *c, const float *b
   }
 }
 
+// The output layer (512 -> 6), whose products are too narrow for the MFMA
+// tiles: BF16 operands, FP32 sums in a fixed order.
+//   forward:  y[r][j] = sum_k h[r][k] W[k][j] + b[j]; a wave per row, lane l
+//             sums k = l, l + 64, ..., then a butterfly over the lanes;
+//   gradient: dW[k][j] = sum_r h[r][k] dY_bf16[r][j] and db[j] = sum_r dY[r][j]
+//             (3,078 values, the order of W4 and b4 in the parameters) as
+//             partial sums over slices of 32 rows, then the slices added by a
+//             wave per value in a fixed order;
+//   input gradient: dh[r][k] = sum_j dY_bf16[r][j] W[k][j], j = 0..5 in order.
+constexpr int kOutW = 512 * 6, kOutWB = 512 * 6 + 6;
+
+__global__ __launch_bounds__(256) void k_out_forward(const __bf16 *__restrict__ h, const __bf16 *__restrict__ w,
+                                                     const float *__restrict__ b, int64_t rows, float *y) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= rows) return;                                    // whole waves
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = lane; k < 512; k += 64) {
+    const float hv = (float)h[r * 512 + k];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc[j] = fmaf(hv, (float)w[k * 6 + j], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    for (int d = 32; d > 0; d >>= 1) acc[j] += __shfl_xor(acc[j], d);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) y[r * 6 + j] = acc[j] + b[j];
+}
+
+__global__ __launch_bounds__(256) void k_out_grad_part(const __bf16 *__restrict__ h, const __bf16 *__restrict__ dyb,
+                                                       const float *__restrict__ dy, int64_t rows, int64_t per,
+                                                       float *part) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= kOutWB) return;
+  const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
+  const bool wgt = v < kOutW;
+  const int k = wgt ? v / 6 : 0, j = wgt ? v - 6 * (v / 6) : v - kOutW;
+  float acc = 0.0f;
+  // 32 rows per step, their loads issued together; the sum runs in row order
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+    float a[32], b[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int64_t r = rb + t;
+      const bool in = r < r1;
+      a[t] = in ? (wgt ? (float)h[r * 512 + k] : 1.0f) : 0.0f;
+      b[t] = in ? (wgt ? (float)dyb[r * 6 + j] : dy[r * 6 + j]) : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) acc = fmaf(a[t], b[t], acc);
+  }
+  part[(int64_t)blockIdx.y * kOutWB + v] = acc;
+}
+
+// One wave per value: lane l adds slices l, l + 64, ... in order, then the
+// lanes are added by a fixed butterfly (the same sum on every run).
+__global__ __launch_bounds__(256) void k_out_grad_join(const float *part, int slices, float *out) {
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= kOutWB) return;                                  // whole waves
+  float acc = 0.0f;
+  for (int s = lane; s < slices; s += 64) acc += part[(int64_t)s * kOutWB + v];
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d);
+  if (lane == 0) out[v] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_out_dh(const __bf16 *__restrict__ dyb, const __bf16 *__restrict__ w,
+                                                int64_t rows, float *dh) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows * 512; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i >> 9;
+    const int k = (int)(i & 511);
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc = fmaf((float)dyb[r * 6 + j], (float)w[k * 6 + j], acc);
+    dh[i] = acc;
+  }
+}
+
 // Gaussian negative log-likelihood head: y [n x 6] -> loss (added to *loss),
 // dY = dL/dy (FP32 for the bias, BF16 for the products).  The log-variance is
 // floored at kLogVarMin (variance 1e-3); below the floor it gets no gradient.
@@ -393,11 +454,12 @@ __global__ __launch_bounds__(256) void k_head(const float *y, const float *t, in
   if (threadIdx.x == 0) unsafeAtomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n);
 }
 
-// The hidden layers' backward epilogue and their bias gradients' first step
-// in one pass: dZ = dH gelu'(Z) (BF16 copy for the products) over a block
-// of 64 columns and a slice of rows, with the slice's column sums formed as
-// k_colsum_part forms them (four row groups, added in order) into
-// part[y][col]; k_colsum_join then adds the slices.
+// The hidden layers' backward epilogue and the first step of their bias
+// gradients in one pass: dZ = dH gelu'(Z) (BF16 copy for the products) over
+// a block of 64 columns and a slice of rows, with the slice's column sums
+// (four row groups, thread g taking rows g, g + 4, ..., the groups added in
+// order) written to part[y][col]; k_colsum_join then adds the slices in
+// order, so the sums do not depend on scheduling.
 __global__ __launch_bounds__(256) void k_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols,
                                                           int64_t per, __bf16 *dzb, float *part) {
   __shared__ float sh[4][64];
@@ -538,6 +600,25 @@ hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int col
   return hipGetLastError();
 }
 
+hipError_t launch_out_forward(const __bf16 *h, const __bf16 *w, const float *b, int64_t rows, float *y,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_out_forward, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, h, w, b, rows, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_backward(const __bf16 *h, const __bf16 *dyb, const float *dy, int64_t rows, const __bf16 *w,
+                               float *gw, float *dh, float *ws, int64_t ws_floats, hipStream_t st) {
+  // slices of 32 rows, longer if their partial sums would not fit the workspace
+  const int64_t max_slices = ws_floats / kOutWB;
+  if (max_slices < 1) return hipErrorInvalidValue;
+  const int64_t per = std::max<int64_t>(32, (rows + max_slices - 1) / max_slices);
+  const int slices = (int)((rows + per - 1) / per);
+  hipLaunchKernelGGL(k_out_grad_part, dim3((kOutWB + 255) / 256, slices), dim3(256), 0, st, h, dyb, dy, rows, per, ws);
+  hipLaunchKernelGGL(k_out_grad_join, dim3((kOutWB + 3) / 4), dim3(256), 0, st, ws, slices, gw);
+  hipLaunchKernelGGL(k_out_dh, dim3(grid_for(rows * 512)), dim3(256), 0, st, dyb, w, rows, dh);
+  return hipGetLastError();
+}
+
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_head, dim3(grid_for(n)), dim3(256), 0, st, y, t, n, dy, dyb, loss);
@@ -550,16 +631,6 @@ void colsum_slices(int64_t rows, int cols, int64_t ws_floats, int64_t *per, int 
   const int64_t slices = std::max<int64_t>(1, std::min<int64_t>({256, (rows + 31) / 32, ws_floats / std::max(1, cols)}));
   *per = (rows + slices - 1) / slices;
   *nsl = (int)((rows + *per - 1) / *per);
-}
-
-hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
-                         hipStream_t st) {
-  int64_t per;
-  int nsl;
-  colsum_slices(rows, cols, ws_floats, &per, &nsl);
-  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, nsl), dim3(256), 0, st, d, rows, cols, per, ws);
-  hipLaunchKernelGGL(k_colsum_join, dim3((cols + 3) / 4), dim3(256), 0, st, ws, nsl, cols, db);
-  return hipGetLastError();
 }
 
 hipError_t launch_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols, __bf16 *dzb, float *db,

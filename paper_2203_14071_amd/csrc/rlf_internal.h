@@ -331,12 +331,19 @@ hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int col
                            hipStream_t st);
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st);
+// The 512 -> 6 output layer: forward y = h W4 + b4 (h BF16 [rows x 512],
+// W4 BF16 [512 x 6], b4 and y FP32), and backward: gw receives dW4 then db4
+// (3,078 FP32, the parameters' order) from h, dY (BF16 for the product, FP32
+// for the bias), dh = dY W4^T FP32 [rows x 512]; ws holds row-slice partials.
+hipError_t launch_out_forward(const __bf16 *h, const __bf16 *w, const float *b, int64_t rows, float *y,
+                              hipStream_t st);
+hipError_t launch_out_backward(const __bf16 *h, const __bf16 *dyb, const float *dy, int64_t rows, const __bf16 *w,
+                               float *gw, float *dh, float *ws, int64_t ws_floats, hipStream_t st);
 // dZ = dH gelu'(Z) as BF16 [rows x cols] and db = column sums of dZ (FP32,
-// summed as launch_colsum sums), ws holding the row slices' partial sums.
+// summed over row slices, then the slices in order), ws holding the slices'
+// partial sums.
 hipError_t launch_gelu_back_colsum(const float *dh, const float *z, int64_t rows, int cols, __bf16 *dzb, float *db,
                                    float *ws, int64_t ws_floats, hipStream_t st);
-hipError_t launch_colsum(const float *d, int64_t rows, int cols, float *db, float *ws, int64_t ws_floats,
-                         hipStream_t st);
 hipError_t launch_gemm_nt(const GemmNTArgs &g, int split_k, hipStream_t st);
 // dst[c][r] = src[r][c] for up to kMaxTransposeJobs BF16 matrices
 // [rows x cols] in one launch.

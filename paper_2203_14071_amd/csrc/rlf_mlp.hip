@@ -174,9 +174,8 @@ int forward_chunk(rlf_mlp *n, const __bf16 *x, int nb, float *y_out) {
     hin = n->h[l];
     kin = kHid;
   }
-  if (int e = gemm(n, hin, kHid, 1, n->wb + kOffW4, kOut, 1, n->cbuf, nb, kOut, kHid)) return e;
-  hipError_t e = launch_bias_act(n->cbuf, n->w + kOffB4, nb, kOut, y_out, nullptr, 0, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "output bias launch");
+  hipError_t e = launch_out_forward(hin, n->wb + kOffW4, n->w + kOffB4, nb, y_out, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "output layer launch");
   return RLF_OK;
 }
 
@@ -449,10 +448,11 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   if (int e = forward_chunk(n, xb, nb, n->y)) return e;
   HIPCHK(c, launch_fill_f64(loss, 1, 0.0, c->stream));
   HIPCHK(c, launch_head(n->y, target, nb, n->dy, n->dyb, loss, c->stream));
-  // output layer: dW4 = h3^T dY, db4 = sum dY, dh3 = dY W4^T
-  if (int e = gemm(n, n->h[2], 1, kHid, n->dyb, kOut, 1, n->g + kOffW4, kHid, kOut, nb)) return e;
-  HIPCHK(c, launch_colsum(n->dy, nb, kOut, n->g + kOffB4, n->ws, kWsFloats, c->stream));
-  if (int e = gemm(n, n->dyb, kOut, 1, n->wb + kOffW4, 1, kOut, n->dh, nb, kHid, kOut)) return e;
+  // output layer: dW4 = h3^T dY, db4 = sum dY (together, in the parameters'
+  // order), dh3 = dY W4^T
+  static_assert(kOffB4 == kOffW4 + (int64_t)kHid * kOut, "b4 follows W4");
+  HIPCHK(c, launch_out_backward(n->h[2], n->dyb, n->dy, nb, n->wb + kOffW4, n->g + kOffW4, n->dh, n->ws, kWsFloats,
+                                c->stream));
   const int64_t offW[3] = {kOffW1, kOffW2, kOffW3}, offB[3] = {kOffB1, kOffB2, kOffB3};
   // the NT GEMM needs the batch dimension in multiples of 8 for the weight gradients
   const bool nt_rows = nb % 8 == 0;

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -216,7 +217,15 @@ def valu_probe(iters=8192, blocks=2048):
                      "wave_instr_per_cu_cycle_at_measured_clock": None if at_clock is None else round(at_clock, 4)})
         log(f"[valu] {name}: {ms.value:.3f} ms, {rate:.3f} wave-instr / CU / cycle at 2.4 GHz; "
             f"clock {hz.value / 1e9:.3f} GHz")
-    return {"clock_hz": CLOCK_HZ, "cus": N_CU, "blocks": blocks, "threads": 256, "iters": iters, "probes": rows}
+    err = ctypes.c_double()
+    L.valu_probe_rsq64_error.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    rc = L.valu_probe_rsq64_error(1 << 24, ctypes.byref(err))
+    if rc != 0:
+        raise RuntimeError(f"v_rsq_f64 accuracy probe: HIP error {rc}")
+    log(f"[valu] v_rsq_f64 largest relative error over 2^24 arguments in [1, 2^40): {err.value:.3g} "
+        f"(2^{math.log2(err.value):.1f})" if err.value > 0 else "[valu] v_rsq_f64 exact on the probe's arguments")
+    return {"clock_hz": CLOCK_HZ, "cus": N_CU, "blocks": blocks, "threads": 256, "iters": iters, "probes": rows,
+            "rsq_f64_max_rel_error": err.value}
 
 
 # Kernel-mix probes (probe/valu_probe.hip): the kernels' own inner loops on

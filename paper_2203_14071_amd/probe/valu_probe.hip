@@ -275,6 +275,29 @@ hipError_t launch_mix(int op, int blocks, const MixArgs &a, hipStream_t st) {
 
 }  // namespace
 
+// Accuracy of v_rsq_f64: for n arguments x = 2^(40 i / n), i < n (spread
+// log-uniformly over [1, 2^40), the range of the profile arguments 1 + s q),
+// the relative error of the instruction against 1 / sqrt(x) from the
+// correctly rounded FP64 square root and division; each block writes its
+// largest error.
+__global__ __launch_bounds__(256) void k_rsq64_error(int64_t n, double *block_max) {
+  __shared__ double sh[256];
+  double worst = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = exp2(40.0 * (double)i / (double)n);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double ref = 1.0 / __dsqrt_rn(x);
+    worst = fmax(worst, fabs(y - ref) / ref);
+  }
+  sh[threadIdx.x] = worst;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_max[blockIdx.x] = sh[0];
+}
+
 extern "C" {
 
 // Number of probe kernels.
@@ -429,6 +452,27 @@ int mix_probe_run(int op, int blocks, int64_t iters, int n_items, int reps, doub
   *clock_hz = hz;
   const double threads = 256.0 * blocks - 64.0;       // the clock wave does no work
   *units = threads * (double)iters * n_items * (op >= kMixFitF64 ? kMixKnots : 1);
+  return (int)e;
+}
+
+// Largest relative error of v_rsq_f64 over n arguments spread over [1, 2^40)
+// (see k_rsq64_error) into *max_rel.  Returns 0, or the HIP error
+// code.  The device buffer is allocated and freed here.
+int valu_probe_rsq64_error(int64_t n, double *max_rel) {
+  if (n < 1 || !max_rel) return (int)hipErrorInvalidValue;
+  constexpr int kBlocks = 1024;
+  double *d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(double) * kBlocks);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_rsq64_error, dim3(kBlocks), dim3(256), 0, 0, n, d);
+    e = hipGetLastError();
+  }
+  double h[kBlocks];
+  if (e == hipSuccess) e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
+  if (d) (void)hipFree(d);
+  double worst = 0.0;
+  for (int b = 0; b < kBlocks && e == hipSuccess; ++b) worst = h[b] > worst ? h[b] : worst;
+  *max_rel = worst;
   return (int)e;
 }
 

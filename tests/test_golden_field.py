@@ -55,3 +55,28 @@ def test_field_golden_consistent_with_oracle(k):
         surf, est = oracle.fit_source(f, cat.flux_jy[s])
         assert np.array_equal(surf, g["sample_surface"][j])
         assert est.e1 == g["e1"][s] and est.e2 == g["e2"][s]
+
+
+def test_config3_sample_golden_consistent_with_oracle():
+    """tests/golden/cfg3_sample_oracle.npz: the sampled sources are the
+    generator's by its stated rule, theta is the oracle's, and every stored
+    estimate is the oracle's estimator on the stored surface."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_cfg3", os.path.join(GOLDEN, "make_cfg3_sample_oracle.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    with np.load(os.path.join(GOLDEN, "cfg3_sample_oracle.npz")) as z:
+        g = {name: z[name] for name in z.files}
+    cfg = synth.CONFIGS[3]
+    cat = synth.catalogue(cfg, synth.rng(3, synth.STREAM_CAT))
+    src = mk.sample_sources(cat)
+    assert list(g["src"]) == src and len(src) == 32
+    assert int(np.argmin(cat.alpha_arcsec)) in src and int(np.argmax(cat.alpha_arcsec)) in src
+    assert np.array_equal(g["theta"], np.array([oracle.facet_theta(cat.alpha_arcsec[s]) for s in src]))
+    i1, i2, e1g, e2g, valid = oracle.e_grid(81, 0.02)
+    for j in range(len(src)):
+        est = oracle.estimate(g["surface"][j], e1g, e2g, valid, 81)
+        assert (est.e1, est.e2, est.s1, est.s2, est.c12, est.lmax, est.argmax, est.n_above, est.flags) == \
+            (g["e1"][j], g["e2"][j], g["s1"][j], g["s2"][j], g["c12"][j], g["lmax"][j], g["argmax"][j],
+             g["n_above"][j], g["flags"][j]), j
+        assert np.all(np.isneginf(g["surface"][j][~valid]))

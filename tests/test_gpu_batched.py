@@ -1,6 +1,7 @@
 """The batched pass (persistent work-queue likelihood, the whole pass captured
 in a HIP graph, autotuned work-item tiles) and the windowed fit with its
 full-grid fallback, through the C ABI."""
+import hashlib
 import math
 import os
 
@@ -12,6 +13,8 @@ from paper_2203_14071_amd import rlf, synth
 from tests import gpu_common as G
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 OUT_KEYS = ("e1", "e2", "s1", "s2", "c12", "lmax", "argmax", "n_above", "flags")
 
@@ -226,6 +229,32 @@ def test_batched_full_size_config3(ctx):
         surf, est = oracle.fit_source(ref, cat.flux_jy[s])
         raw, adj, wl, fl = G.check_estimate_matched(h2, s, surf, h2["surface"][rows[s]], ll_tol, band, 1e-4, est)
         print(f"config 3 pass, source {s} ({ref.n_cells} cells): |de| {raw:.2e}, |dl| / delta {wl:.3f}")
+    # 32 more sources across the range of sizes against stored oracle results
+    # (tests/golden/cfg3_sample_oracle.npz, written by
+    # tests/golden/make_cfg3_sample_oracle.py from the oracle alone)
+    with np.load(os.path.join(GOLDEN, "cfg3_sample_oracle.npz")) as z:
+        g = {name: z[name] for name in z.files}
+    gs = [int(v) for v in g["src"]]
+    assert int(g["n_rows"]) == o.n_rows and int(g["n_chan"]) == o.n_chan and len(gs) == 32
+    assert cells2[gs].min() <= np.quantile(cells2, 0.01)      # the smallest facets ...
+    assert np.count_nonzero(cells2[gs] >= 1024) >= 3         # ... to the largest bucket this field fills
+    # every weight lands in each facet: summed in different orders, |dW| <= (n - 1) u W
+    wrel = 2.3e-16 * o.n_rows * o.n_chan
+    gsurf = out2["surface"][gs].cpu().numpy()
+    worst_de, worst_l, flips = 0.0, 0.0, 0
+    for j, s in enumerate(gs):
+        a, b = fac2["offsets"][s], fac2["offsets"][s + 1]
+        assert b - a == g["n_cells"][j], s
+        hsh = hashlib.sha256()
+        for arr in (fac2["ix"][a:b], fac2["iy"][a:b], fac2["count"][a:b]):
+            hsh.update(np.ascontiguousarray(arr, dtype=np.int32).tobytes())
+        assert np.array_equal(np.frombuffer(hsh.digest(), dtype=np.uint8), g["cells_sha256"][j]), s
+        assert fac2["theta"][s] == g["theta"][j], s
+        assert abs(np.sum(fac2["wsum"][a:b]) - g["wsum_total"][j]) <= wrel * g["wsum_total"][j], s
+        raw, adj, wl, fl = G.check_estimate_matched(h2, s, g["surface"][j], gsurf[j], ll_tol, band, 1e-4)
+        worst_de, worst_l, flips = max(worst_de, raw), max(worst_l, wl), flips + int(fl)
+    print(f"config 3, 32 stored sources ({cells2[gs].min()}-{cells2[gs].max()} cells): max |de| {worst_de:.2e}, "
+          f"max |dl| / delta {worst_l:.3f}, threshold flips {flips}")
     ps2.free()
     f2.free()
     mctx.close()

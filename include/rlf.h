@@ -297,7 +297,11 @@ typedef struct {
  * with w_{s,k} the natural-cubic-spline quadrature weight of knot k times the
  * log-normal prior density at alpha_k.  Then Lmax, the set
  * {ln L >= ln Lmax + ln frac}, its likelihood-weighted mean and covariance,
- * and the flags. */
+ * and the flags.  RLF_MIXED: the set is decided in FP64 -- the maximum and
+ * every point whose FP32-sum ln L lies within 2^-16 (|ln Lmax| + 64) of the
+ * threshold are evaluated again with FP64 sums over an FP64 copy of the
+ * facet's cells before the set is formed (every mode, except on facets with
+ * position marginalisation); the surface holds the re-evaluated values. */
 int rlf_fit_sources(rlf_ctx *ctx, const rlf_facets *facets, const rlf_fit_opts *opts,
                     rlf_fit_out *out);
 

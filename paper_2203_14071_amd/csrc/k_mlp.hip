@@ -426,14 +426,18 @@ __global__ __launch_bounds__(256) void k_out_dh(const __bf16 *__restrict__ dyb, 
   }
 }
 
-// Gaussian negative log-likelihood head: y [n x 6] -> loss (added to *loss),
-// dY = dL/dy (FP32 for the bias, BF16 for the products).  The log-variance is
-// floored at kLogVarMin (variance 1e-3); below the floor it gets no gradient.
-__global__ __launch_bounds__(256) void k_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb,
-                                              double *loss) {
-  __shared__ double sh[4];
+// Gaussian negative log-likelihood head: y [n x 6] -> loss (written to
+// *loss), dY = dL/dy (FP32 for the bias, BF16 for the products).  The
+// log-variance is floored at kLogVarMin (variance 1e-3); below the floor it
+// gets no gradient.  One block of 1024 threads: thread i takes rows i, i +
+// 1024, ... and the loss terms are added in a fixed order (per thread, then
+// a butterfly within each wave, then the waves in order), so the loss is the
+// same on every run.
+__global__ __launch_bounds__(1024) void k_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb,
+                                               double *loss) {
+  __shared__ double sh[16];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     for (int d = 0; d < 3; ++d) {
       const float mu = y[i * 6 + d], s_raw = y[i * 6 + 3 + d];
       const float s = fmaxf(s_raw, kLogVarMin);
@@ -451,7 +455,11 @@ __global__ __launch_bounds__(256) void k_head(const float *y, const float *t, in
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) unsafeAtomicAdd(loss, (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n);
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += sh[w];
+    *loss = total / (double)n;
+  }
 }
 
 // The hidden layers' backward epilogue and the first step of their bias
@@ -621,7 +629,7 @@ hipError_t launch_out_backward(const __bf16 *h, const __bf16 *dyb, const float *
 
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_head, dim3(grid_for(n)), dim3(256), 0, st, y, t, n, dy, dyb, loss);
+  hipLaunchKernelGGL(k_head, dim3(1), dim3(1024), 0, st, y, t, n, dy, dyb, loss);
   return hipGetLastError();
 }
 

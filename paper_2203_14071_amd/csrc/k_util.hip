@@ -27,10 +27,6 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n, double v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
 // dst[idx[i]] = src[i] (| bits for the 32-bit form), i < n; idx in range by
 // construction of the caller.
 __global__ __launch_bounds__(256) void k_scatter_f64(const double *src, const int32_t *idx, int64_t n, double *dst) {
@@ -72,12 +68,6 @@ hipError_t launch_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -325,7 +325,6 @@ hipError_t launch_scatter_f64(const double *src, const int32_t *idx, int64_t n, 
 hipError_t launch_scatter_u32(const uint32_t *src, const int32_t *idx, int64_t n, uint32_t bits, uint32_t *dst,
                               hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
-hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs &g, int split_k, hipStream_t st);
 hipError_t launch_bias_act(const float *c, const float *b, int64_t rows, int cols, float *z, __bf16 *h, int act,
                            hipStream_t st);

@@ -446,7 +446,6 @@ int rlf_mlp_train_step(rlf_mlp *n, const void *x, const float *target, int64_t r
   const int nb = (int)rows;
   const __bf16 *xb = reinterpret_cast<const __bf16 *>(x);
   if (int e = forward_chunk(n, xb, nb, n->y)) return e;
-  HIPCHK(c, launch_fill_f64(loss, 1, 0.0, c->stream));
   HIPCHK(c, launch_head(n->y, target, nb, n->dy, n->dyb, loss, c->stream));
   // output layer: dW4 = h3^T dY, db4 = sum dY (together, in the parameters'
   // order), dh3 = dY W4^T

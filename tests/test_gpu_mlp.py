@@ -229,10 +229,13 @@ def test_training_reduces_loss_and_resumes_bit_exactly(ctx):
     st = net.get_state()
     net2 = rlf.Mlp(ctx, max_batch=256)
     net2.set_state(st["params"], st["m"], st["v"], st["step"])
+    loss2 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
     for step in range(5):
         b = (step % 4) * 256
         net.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss)
-        net2.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss)
+        net2.train_step(xd[b:b + 256], td[b:b + 256], 1e-3, loss2)
+        ctx.sync()
+        assert loss.item() == loss2.item(), step          # the loss is summed in a fixed order
     a, c = net.get_state(), net2.get_state()
     assert np.array_equal(a["params"], c["params"]) and np.array_equal(a["m"], c["m"])
     assert a["step"] == c["step"] == 65

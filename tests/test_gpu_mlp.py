@@ -67,11 +67,14 @@ def test_forward_matches_oracle(ctx):
     net.free()
 
 
-def test_train_step_gradients_and_adam_match_oracle(ctx):
+@pytest.mark.parametrize("n", [200, 37])
+def test_train_step_gradients_and_adam_match_oracle(ctx, n):
+    """n = 200: the NT products for every weight gradient; n = 37 (not a
+    multiple of 8): the strided products, and a last 5-row slice in the
+    output layer's gradient sums."""
     torch = G.torch_cuda()
     p = _init(9)
     rng = np.random.default_rng(10)
-    n = 200
     x = M.bf16(rng.standard_normal((n, M.N_IN)) * 0.2)
     t = rng.standard_normal((n, 3)) * 0.3
     net = rlf.Mlp(ctx, max_batch=256)

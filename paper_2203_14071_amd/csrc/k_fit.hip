@@ -255,10 +255,13 @@ __global__ __launch_bounds__(256) void k_refine_eval(FitArgs a, RefineArgs r, in
 }
 
 
-// Grid launch: blockIdx.y = source, one thread per valid grid point.
+// Grid launch: blockIdx.y = source (largest facets first when a.size_order
+// is set: blocks are dispatched in index order, and the long blocks of the
+// largest facets then do not trail the launch), one thread per valid grid
+// point.
 template <int R, bool kExact, bool kMixed, int NP = 0>
 __global__ __launch_bounds__(256) void k_fit(FitArgs a, int num_r) {
-  const int s = blockIdx.y;
+  const int s = a.size_order ? a.size_order[a.n_src - 1 - (int)blockIdx.y] : (int)blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n_valid) return;
   if (a.redo && !a.redo[s]) return;
@@ -340,10 +343,11 @@ __global__ __launch_bounds__(256) void k_fit_join(FitArgs a) {
 // with a check stride S, per lattice point c + S q (both axes, |q| <= c / S)
 // outside the box; invalid points (|e| >= 1) are skipped.  No other point is
 // evaluated (the estimator reads no other).  Blocks past a source's positions
-// leave at once, so the grid is sized for the largest possible box.
+// leave at once, so the grid is sized for the largest possible box.  Sources
+// largest facet first, as in k_fit.
 template <int R, bool kExact, bool kMixed>
 __global__ __launch_bounds__(256) void k_fit_window(FitArgs a, int num_r) {
-  const int s = blockIdx.y;
+  const int s = a.size_order ? a.size_order[a.n_src - 1 - (int)blockIdx.y] : (int)blockIdx.y;
   // lattice pass 1: the lattice alone (an empty box); pass 2: the lattice
   // values are already in the surface, only the box is evaluated
   int4 b = a.lattice_pass == 1 ? make_int4(1, 0, 1, 0) : reinterpret_cast<const int4 *>(a.window)[s];

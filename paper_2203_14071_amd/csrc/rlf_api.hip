@@ -1220,6 +1220,7 @@ int fit_args(rlf_ctx *c, const rlf_facets *f, FitArgs &fa) {
   fa.fit64 = f->cells.fit64;
   fa.fit32 = f->cells.fit32;
   fa.lsurf = f->d_lsurf;
+  fa.size_order = f->d_order;
   if (f->pos_side > 1) {
     PosPrepArgs pa{};
     pa.n_src = (int32_t)f->n_src;

@@ -176,6 +176,9 @@ struct FitArgs {
   // [n_src][parts][2 * num_r][n_valid] go to part_sums before being joined
   int32_t parts;
   double *part_sums;
+  // sources by increasing facet size (null: catalogue order); the full-grid
+  // launch takes them from the largest, so the longest blocks start first
+  const int32_t *size_order;
 };
 
 // Cross-correlation data of the position marginalisation (one row of n_pos

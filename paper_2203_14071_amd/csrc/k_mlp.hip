@@ -429,27 +429,74 @@ __global__ __launch_bounds__(256) void k_out_dh(const __bf16 *__restrict__ dyb, 
 // Gaussian negative log-likelihood head: y [n x 6] -> loss (written to
 // *loss), dY = dL/dy (FP32 for the bias, BF16 for the products).  The
 // log-variance is floored at kLogVarMin (variance 1e-3); below the floor it
-// gets no gradient.  One block of 1024 threads: thread i takes rows i, i +
-// 1024, ... and the loss terms are added in a fixed order (per thread, then
-// a butterfly within each wave, then the waves in order), so the loss is the
-// same on every run.
-__global__ __launch_bounds__(1024) void k_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb,
-                                               double *loss) {
+// gets no gradient.  Blocks of 1024 threads.  Block 0 forms the loss: thread
+// i takes rows i, i + 1024, ... and the terms are added in a fixed order
+// (per thread, then a butterfly within each wave, then the waves in order),
+// so the loss is the same on every run; it loads kHeadRows rows at a time
+// before adding any.  Blocks 1, 2, ... write dY, a row per thread, so that
+// the strided loads and stores of a large batch are spread over as many CUs
+// (one block's memory pipeline took 17 us for 4096 rows).  Both compute the
+// terms by the same expressions (head_terms).
+constexpr int kHeadRows = 4;
+
+__device__ __forceinline__ void head_terms(float mu, float s_raw, float tv, float nf, double *lt, float *gm,
+                                           float *gs) {
+  const float s = fmaxf(s_raw, kLogVarMin);
+  const float e = tv - mu;
+  const float ie = expf(-s);
+  *lt = 0.5 * ((double)s + (double)e * e * ie);
+  *gm = -e * ie / nf;
+  *gs = s_raw < kLogVarMin ? 0.0f : 0.5f * (1.0f - e * e * ie) / nf;
+}
+
+__global__ __launch_bounds__(1024) void k_head(const float *__restrict__ y, const float *__restrict__ t, int64_t n,
+                                               float *__restrict__ dy, __bf16 *__restrict__ dyb,
+                                               double *__restrict__ loss) {
   __shared__ double sh[16];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  const int64_t stride = blockDim.x;
+  if (blockIdx.x > 0) {
+    const int64_t i = (int64_t)(blockIdx.x - 1) * stride + threadIdx.x;
+    if (i >= n) return;
+    float yv[6], tv[3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) yv[c] = y[i * 6 + c];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tv[d] = t[i * 3 + d];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float mu = y[i * 6 + d], s_raw = y[i * 6 + 3 + d];
-      const float s = fmaxf(s_raw, kLogVarMin);
-      const float e = t[i * 3 + d] - mu;
-      const float ie = expf(-s);
-      acc += 0.5 * ((double)s + (double)e * e * ie);
-      const float gm = -e * ie / (float)n;
-      const float gs = s_raw < kLogVarMin ? 0.0f : 0.5f * (1.0f - e * e * ie) / (float)n;
+      double lt;
+      float gm, gs;
+      head_terms(yv[d], yv[3 + d], tv[d], (float)n, &lt, &gm, &gs);
       dy[i * 6 + d] = gm;
       dy[i * 6 + 3 + d] = gs;
       dyb[i * 6 + d] = to_bf16(gm);
       dyb[i * 6 + 3 + d] = to_bf16(gs);
+    }
+    return;
+  }
+  double acc = 0.0;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += kHeadRows * stride) {
+    float yv[kHeadRows][6], tv[kHeadRows][3];
+#pragma unroll
+    for (int u = 0; u < kHeadRows; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) yv[u][c] = y[i * 6 + c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) tv[u][d] = t[i * 3 + d];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kHeadRows; ++u) {
+      if (i0 + u * stride >= n) break;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double lt;
+        float gm, gs;
+        head_terms(yv[u][d], yv[u][3 + d], tv[u][d], (float)n, &lt, &gm, &gs);
+        acc += lt;
+      }
     }
   }
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d);
@@ -629,7 +676,7 @@ hipError_t launch_out_backward(const __bf16 *h, const __bf16 *dyb, const float *
 
 hipError_t launch_head(const float *y, const float *t, int64_t n, float *dy, __bf16 *dyb, double *loss,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(1024), 0, st, y, t, n, dy, dyb, loss);
+  hipLaunchKernelGGL(k_head, dim3(1 + (int)((n + 1023) / 1024)), dim3(1024), 0, st, y, t, n, dy, dyb, loss);
   return hipGetLastError();
 }
 

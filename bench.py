@@ -30,11 +30,13 @@ METRIC = "sources fitted/s + Gvis/s at 1k-source SKA-MID field; surrogate vs pla
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
 # Algorithmic FLOPs of the likelihood grid (FMA = 2):
-#   per (cell, grid point): A^{-T} k and its squared norm: 2 MUL + 3 FMA      =  9
-#   per (cell, grid point, knot): x = 1 + s q (FMA), x^{-3/2} (rsqrt + 2 MUL),
-#   D += W Re(Vbar) f (FMA), Mm += (W f) f (MUL + FMA)                      = 10
+#   per (cell, grid point): A^{-T} k and its squared norm: 3 MUL + 3 FMA      =  9
+#   per (cell, grid point, knot), with sqrt(W) carried in the profile's scale
+#   (cell records (W^{-1/6} k, W^{-1/3}, sqrt(W) Re Vbar): h = sqrt(W) f):
+#   x' = W^{-1/3} + s q' (FMA), h = x'^{-3/2} (rsqrt + 2 MUL),
+#   D += sqrt(W) Re(Vbar) h (FMA), Mm += h h (FMA)                          =  9
 FIT_FLOP_CELL_POINT = 9
-FIT_FLOP_CELL_POINT_KNOT = 10
+FIT_FLOP_CELL_POINT_KNOT = 9
 # Algorithmic FLOPs per (visibility, source) pair, FMA = 2 and one per
 # elementary function value (sin, cos, x^{-3/2}, round to integer):
 #   extraction: phase u l + v m + w n1 (MUL + 2 FMA) 5, sin + cos 2,
@@ -66,7 +68,9 @@ TRAFFIC_BYTES = {"fp64": {"extract": 2834.0e6, "fit": 357.2e6, "model": 521.0e6}
 # which have no instruction, 4 each plus 2 for the reduction to one turn.
 # Products formed once per visibility (u^2, uv, v^2, shared by every source)
 # or once per (cell, e point) (the quadratic form, shared by the knots) are
-# counted where they are formed.
+# counted where they are formed.  The likelihood's cell records carry
+# sqrt(W) in the profile's scale (h = sqrt(W) f), so D and M take one FMA
+# each per knot.
 SLOT_PEAK = 256 * 64 * 2.4e9
 SLOT_ITEMS = {
     "fp64": {
@@ -77,7 +81,7 @@ SLOT_ITEMS = {
                     "cell index 2 mul + 2 rint + key": 5, "cell test": 1, "shape form 3 FMA": 3,
                     "rsqrt": 4, "cube 2": 2, "rotation + own model + accumulate 5 FMA": 5, "weight sum": 1},
         # per (cell, e point, knot)
-        "fit": {"profile argument": 1, "rsqrt": 4, "cube 2": 2, "D and M 3": 3,
+        "fit": {"profile argument": 1, "rsqrt": 4, "cube 2": 2, "D and M 2 FMA": 2,
                 "quadratic form 6 per (cell, e point) over 20 knots": 0.3},
     },
     "mixed": {
@@ -87,7 +91,7 @@ SLOT_ITEMS = {
                     "cell index 2 mul + 2 rint + key": 5, "cell test": 1, "rotation 4": 4,
                     "shape form 3 FMA": 3, "rsqrt": 1, "cube 2": 2, "weight x flux": 1, "own model add": 1,
                     "widen 2 cvt": 2, "accumulate 2 FMA (FP64)": 2, "weight sum": 1},
-        "fit": {"profile argument": 1, "rsqrt": 1, "cube 2": 2, "D and M 3": 3,
+        "fit": {"profile argument": 1, "rsqrt": 1, "cube 2": 2, "D and M 2 FMA": 2,
                 "quadratic form 6 per (cell, e point) over 20 knots": 0.3,
                 "widening of the 32-cell FP32 sums (4 per 32 cells)": 0.125},
     },

@@ -102,11 +102,16 @@ __global__ __launch_bounds__(256) void k_write(CompactArgs a) {
       a.cells.wsum[o] = W;
       a.cells.vre[o] = vr;
       a.cells.vim[o] = vi;
+      // likelihood records with sqrt(W) carried by the profile: with
+      // c = W^{-1/3}, sqrt(W) f(x) = (c x)^{-3/2} and c x = c + s_k |A^{-T} k'|^2
+      // for the cell centre k' = W^{-1/6} (uc, vc), so a knot's terms are
+      // h = (c + s_k q')^{-3/2}, D += (sqrt(W) Re Vbar) h, M += h h
       const double uc = (double)ix / theta, vc = (double)iy / theta;
+      const double cw = 1.0 / cbrt(W), rw = sqrt(cw), b = sqrt(W) * vr;
       // the mixed form's fit runs on the FP32 records; its estimator
       // rechecks the points at its decisions on the FP64 ones
-      if (kMixed) a.cells.fit32[o] = make_float4((float)uc, (float)vc, (float)W, (float)(W * vr));
-      a.cells.fit64[o] = make_double4(uc, vc, W, W * vr);
+      if (kMixed) a.cells.fit32[o] = make_float4((float)(uc * rw), (float)(vc * rw), (float)cw, (float)b);
+      a.cells.fit64[o] = make_double4(uc * rw, vc * rw, cw, b);
     }
     out += total;
   }

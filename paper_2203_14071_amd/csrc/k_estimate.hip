@@ -49,9 +49,9 @@ __device__ double loglike_f64_wave(const EstimateArgs &a, int s, double e1, doub
       const double q = fma(ku, ku, kv * kv);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double f = pow_m32_f64(fma(sk[k], q, 1.0));         // (2/3) f_c
-        D[k] = fma(cl.w, f, D[k]);
-        M[k] = fma(cl.z * f, f, M[k]);
+        const double h = pow_m32_f64(fma(sk[k], q, cl.z));        // (2/3) sqrt(W) f_c
+        D[k] = fma(cl.w, h, D[k]);
+        M[k] = fma(h, h, M[k]);
       }
     }
 #pragma unroll

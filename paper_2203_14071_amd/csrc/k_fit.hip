@@ -6,10 +6,13 @@
 //   ln L(e) = m + ln sum_k exp(ln w_k + ln L(e, alpha_k) - m)   (scale marginalised)
 //
 // One thread per grid point, all knots of that point in registers (D_k, M_k),
-// a uniform loop over the source's cells: each cell (uc, vc, W, W Re Vbar)
-// comes in through one scalar load shared by the wave.  Per (cell, point)
-// the quadratic form costs 7 ops and serves all knots; per (cell, point,
-// knot): 1 FMA, x^(-3/2), 1 FMA, 1 MUL + 1 FMA.
+// a uniform loop over the source's cells: each cell record comes in through
+// one scalar load shared by the wave; it carries sqrt(W_c) in the profile's
+// scale, (W^{-1/6} uc, W^{-1/6} vc, W^{-1/3}, sqrt(W) Re Vbar), so that
+// h = (W^{-1/3} + s_k q')^{-3/2} = sqrt(W_c) f_c (q' the quadratic form of the
+// scaled centre).  Per (cell, point) the quadratic form costs 6 ops and
+// serves all knots; per (cell, point, knot): 1 FMA, x^(-3/2), 2 FMAs
+// (D += b h, M += h h).
 //   FP64 form:  x^(-3/2) as v_rsq_f64 cubed with a first-order correction
 //               (5 ops, relative error < 3e-14), computed as (2/3) x^(-3/2).
 //   Mixed form: FP32 cell data and arithmetic (v_rsq_f32 cubed), partial sums of
@@ -23,8 +26,10 @@
 //   ln L(e) = ln sum_k w_k (1/n_pos) sum_p exp(D_kp^2 / (2 M_k) - ln(M_k) / 2).
 // The knots run in blocks of KB with the KB * n_pos sums of a block in
 // registers; the n_pos values of a cell come in through scalar loads (one
-// row of G per cell), so a (cell, point, knot) costs the profile (6 ops), M
-// (2) and one FMA per offset, plus the quadratic form once per knot block.
+// row of G per cell, G carrying sqrt(W_c) as the records do: the profile
+// term h is sqrt(W_c) f_c), so a (cell, point, knot) costs the profile (6
+// ops), M (1) and one FMA per offset, plus the quadratic form once per knot
+// block.
 #include "rlf_cellsums.h"
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
@@ -136,8 +141,8 @@ __device__ __forceinline__ double loglike_pos(const FitArgs &a, int num_r, int s
         const double *gc = G + c * NP;
 #pragma unroll
         for (int b = 0; b < KB; ++b) {
-          const double f = pow_m32_f64(fma(sk[b], q, 1.0));         // (2/3) f_c
-          M[b] = fma(cl.z * f, f, M[b]);
+          const double f = pow_m32_f64(fma(sk[b], q, cl.z));        // (2/3) sqrt(W) f_c
+          M[b] = fma(f, f, M[b]);
 #pragma unroll
           for (int p = 0; p < NP; ++p) D[b][p] = fma(f, gc[p], D[b][p]);
         }
@@ -165,9 +170,9 @@ __device__ __forceinline__ double loglike_pos(const FitArgs &a, int num_r, int s
           const float *gc = G + (cb + t) * NP;
 #pragma unroll
           for (int b = 0; b < KB; ++b) {
-            const float r = __builtin_amdgcn_rsqf(fmaf(sk[b], q, 1.0f));
-            const float f = r * r * r;
-            m[b] = fmaf(cl.z * f, f, m[b]);
+            const float r = __builtin_amdgcn_rsqf(fmaf(sk[b], q, cl.z));
+            const float f = r * r * r;                                // sqrt(W) f_c
+            m[b] = fmaf(f, f, m[b]);
 #pragma unroll
             for (int p = 0; p < NP; ++p) d[b][p] = fmaf(f, gc[p], d[b][p]);
           }

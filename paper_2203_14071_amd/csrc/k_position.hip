@@ -1,8 +1,9 @@
 // Position marginalisation (Sec. 2.4): the cross-correlation data of every
 // compacted cell c and position offset x_p = (dl_p, dm_p),
-//   G[c, p] = W_c Re(Vbar_c exp(-2 pi i (uc_c dl_p + vc_c dm_p))),
-// so that the likelihood kernels form D(x_p) = sum_c f_c G[c, p] with the
-// same profile values f_c for every offset.  Offsets: an n_side x n_side
+//   G[c, p] = sqrt(W_c) Re(Vbar_c exp(-2 pi i (uc_c dl_p + vc_c dm_p))),
+// so that the likelihood kernels form D(x_p) = sum_c h_c G[c, p] with the
+// same profile values h_c = sqrt(W_c) f_c (as the cell records give them)
+// for every offset.  Offsets: an n_side x n_side
 // grid at spacing `step` (radians) centred on the catalogue position,
 // p = p1 * n_side + p2, dl = (p1 - h) step, dm = (p2 - h) step,
 // h = (n_side - 1) / 2.  One block per source, a thread per cell; the
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(256) void k_pos_prep(PosPrepArgs a) {
         const double dm = (double)(p2 - h) * a.step;
         double sn, cs;
         sincospi(2.0 * fma(uc, dl, vc * dm), &sn, &cs);
-        const double g = W * fma(vr, cs, vi * sn);
+        const double g = sqrt(W) * fma(vr, cs, vi * sn);
         const int64_t o = c * a.n_pos + p1 * a.n_side + p2;
         if (kMixed)
           a.g32[o] = (float)g;

@@ -55,7 +55,7 @@ struct Cells {
   int64_t *n_nonempty;       // [n_src]
   int32_t *ix, *iy, *count;
   double *wsum, *vre, *vim;
-  double4 *fit64;            // (uc, vc, W, W Re Vbar) for the FP64 fit
+  double4 *fit64;            // (W^{-1/6} uc, W^{-1/6} vc, W^{-1/3}, sqrt(W) Re Vbar) for the FP64 fit
   float4 *fit32;             // same in FP32 for the mixed fit
 };
 

@@ -86,7 +86,7 @@ SLOT_ITEMS = {
     },
     "mixed": {
         "model": {"phase 3 FMA (FP64)": 3, "fractional turn": 1, "cvt": 1, "sin + cos": 2,
-                  "shape form 3 FMA (flux folded in)": 3, "rsqrt": 1, "cube 2": 2, "accumulate 2 FMA": 2},
+                  "shape form 3 FMA": 3, "rsqrt": 1, "cube and flux 3": 3, "accumulate 2 FMA": 2},
         "extract": {"phase 3 FMA (FP64)": 3, "fractional turn": 1, "cvt": 1, "sin + cos": 2,
                     "cell index 2 mul + 2 rint + key": 5, "cell test": 1, "rotation 4": 4,
                     "shape form 3 FMA": 3, "rsqrt": 1, "cube 2": 2, "weight x flux": 1, "own model add": 1,

@@ -9,7 +9,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <limits>
 #include <string>
 #include <mutex>
 #include <vector>
@@ -183,12 +182,6 @@ SrcMixed to_mixed(const SrcModel &m) {
   r.q12x2 = (float)m.q12x2;
   r.q22 = (float)m.q22;
   r.theta = m.theta;
-  const double fmax32 = (double)std::numeric_limits<float>::max();
-  const double c0 = m.flux > 0.0 ? std::min(std::pow(m.flux, -2.0 / 3.0), fmax32) : fmax32;
-  r.c0 = (float)c0;
-  r.q11s = (float)std::min(m.q11 * c0, fmax32);
-  r.q12x2s = (float)std::max(std::min(m.q12x2 * c0, fmax32), -fmax32);
-  r.q22s = (float)std::min(m.q22 * c0, fmax32);
   return r;
 }
 

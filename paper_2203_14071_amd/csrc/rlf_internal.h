@@ -24,14 +24,11 @@ struct alignas(64) SrcModel {
 static_assert(sizeof(SrcModel) == 64, "one 64-byte scalar load per source");
 
 // The same constants for the mixed-precision form: phase terms stay FP64,
-// the profile runs in FP32.  The sky model takes the flux inside its profile
-// argument: with c0 = S^{-2/3}, (c0 x)^{-3/2} = S x^{-3/2}, so its term needs
-// no multiplication by S (c0 = FLT_MAX for S = 0: the term underflows to 0).
+// the profile runs in FP32.
 struct alignas(64) SrcMixed {
   double l, m, n1;
   float flux, q11, q12x2, q22;
   double theta;
-  float c0, q11s, q12x2s, q22s;   // c0 and c0 q11, c0 q12x2, c0 q22 (each at most FLT_MAX)
 };
 static_assert(sizeof(SrcMixed) == 64, "one 64-byte scalar load per source");
 

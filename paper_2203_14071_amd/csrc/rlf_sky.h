@@ -5,8 +5,11 @@
 //   sum_f64:   FP64 phase, exact reduction + table exp (cis2pi_f64), the
 //              profile by the corrected rsqrt cube; returns the sum of
 //              S exp(2 pi i phi) / x^{3/2} (without the spectral factor).
-//   sum_mixed: FP64 phase and fractional part, FP32 sin/cos, profile (the
-//              flux folded into its argument), sum.
+//   sum_mixed: FP64 phase and fractional part, FP32 sin/cos, profile, sum.
+// The flux stays a multiplication: folded into the profile argument (as the
+// FP64 extraction does with per-lane sources) the innermost FMA would take
+// two wave-uniform scalar operands, which one VOP3 instruction cannot read,
+// and the compiler's move to a VGPR costs what the multiplication saved.
 #pragma once
 
 #include "rlf_devmath.h"
@@ -49,9 +52,9 @@ __device__ __forceinline__ float2 sum_mixed(double u, double v, double w, const 
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
     const float t = (float)__builtin_amdgcn_fract(ph);      // turns, in [0, 1]
     const float sn = __builtin_amdgcn_sinf(t), cs = __builtin_amdgcn_cosf(t);
-    const float x = fmaf(p.q11s, uu, fmaf(p.q12x2s, uv, fmaf(p.q22s, vv, p.c0)));   // S^{-2/3} x
+    const float x = fmaf(p.q11, uu, fmaf(p.q12x2, uv, fmaf(p.q22, vv, 1.0f)));
     const float r = __builtin_amdgcn_rsqf(x);
-    const float amp = r * r * r;                                                    // S x^{-3/2}
+    const float amp = p.flux * (r * r * r);
     ar = fmaf(amp, cs, ar);
     ai = fmaf(amp, sn, ai);
   };

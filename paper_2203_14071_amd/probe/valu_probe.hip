@@ -374,13 +374,9 @@ int mix_probe_run(int op, int blocks, int64_t iters, int n_items, int reps, doub
     // sources over a 1-degree field, scale lengths ~1 arcsec; cells on a
     // 17 x 17 patch of a 5,400-wavelength facet lattice
     const double l = 8.7e-3 * ((i * 37) % 101 - 50) / 50.0, m = 8.7e-3 * ((i * 53) % 97 - 48) / 48.0;
-    // (records as the library packs them: a 100 uJy source; the mixed
-    // record's sky-model profile carries the flux, c0 = S^{-2/3})
-    const double q = 4e-10 * (1.0 + (i % 7) * 0.1), flux = 1e-4;
-    const double c0m = std::pow(flux, -2.0 / 3.0);
-    hs[i] = rlf::SrcModel{l, m, -0.5 * (l * l + m * m), flux, q, 0.2 * q, 1.1 * q, 1.8e-4};
-    hm[i] = rlf::SrcMixed{l, m, -0.5 * (l * l + m * m), (float)flux, (float)q, (float)(0.2 * q), (float)(1.1 * q), 1.8e-4,
-                          (float)c0m, (float)(c0m * q), (float)(c0m * 0.2 * q), (float)(c0m * 1.1 * q)};
+    const double q = 4e-10 * (1.0 + (i % 7) * 0.1);
+    hs[i] = rlf::SrcModel{l, m, -0.5 * (l * l + m * m), 1e-4, q, 0.2 * q, 1.1 * q, 1.8e-4};
+    hm[i] = rlf::SrcMixed{l, m, -0.5 * (l * l + m * m), 1e-4f, (float)q, (float)(0.2 * q), (float)(1.1 * q), 1.8e-4};
     // cells as the library packs them: (W^{-1/6} uc, W^{-1/6} vc, W^{-1/3}, sqrt(W) Re Vbar)
     const double uc = 5400.0 * (i % 17 - 8), vc = 5400.0 * ((i / 17) % 17 - 8);
     const double W = 1.0 + 1e-3 * i, cw = 1.0 / std::cbrt(W), rw = std::sqrt(cw), b = std::sqrt(W) * 1e-3 * (i % 13);

@@ -36,7 +36,15 @@ namespace rlf {
 namespace {
 
 constexpr int kXcd = 8;
-constexpr int kWaves = 4;          // waves per block
+constexpr int kWaves = 4;          // waves per block (1024-entry table or none)
+// FP64 launches of at least kBigTableTiles source tiles take a 2048-entry
+// table (32 KB of LDS: sin's x^5 term drops, one FMA per pair) in blocks of
+// 8 waves, so that four blocks per CU keep eight waves per SIMD in 128 KB;
+// smaller launches, whose blocks hold idle waves, keep the 16 KB table and
+// four-wave blocks (eight blocks per CU)
+constexpr int kBigTableTiles = 8;
+template <bool kMixed, int T>
+constexpr int waves_per_block() { return (!kMixed && T == 2048) ? 8 : kWaves; }
 constexpr int kNsF64 = 1, kNsMixed = 1;        // sources per lane
 constexpr int kGroupF64 = 2, kGroupMixed = 4;  // visibilities whose scalar loads are issued together
 constexpr double kNoRun = 1099511627776.0;    // 2^40: "no open run" (run keys are below 2^31 in magnitude)
@@ -133,22 +141,23 @@ __device__ __forceinline__ void enter_cell(LaneSrc &L, double4 *__restrict__ acc
 // steers the scalar registers: a minimum of 7 waves gives 94 SGPRs with two
 // spilled to VGPR lanes and measured 4.5 % faster than 6 (97 SGPRs, none
 // spilled), while 8 spills 17 and is 15 % slower.
-template <bool kMixed, int NS, int G>
-__global__ __launch_bounds__(256, kMixed ? 7 : 8) void k_extract(ExtractArgs a, const double4 *__restrict__ sgeo,
-                                                 const void *__restrict__ squad, const void *__restrict__ sres,
-                                                 const uint64_t *__restrict__ swt,
-                                                 double4 *__restrict__ acc) {
-  __shared__ double2 tab[kMixed ? 1 : kCisTable];
+// T: entries of the FP64 form's exp table (1024 or 2048; the mixed form has none).
+template <bool kMixed, int NS, int G, int T>
+__global__ __launch_bounds__((64 * waves_per_block<kMixed, T>()), kMixed ? 7 : 8) void k_extract(
+    ExtractArgs a, const double4 *__restrict__ sgeo, const void *__restrict__ squad, const void *__restrict__ sres,
+    const uint64_t *__restrict__ swt, double4 *__restrict__ acc) {
+  constexpr int kW = waves_per_block<kMixed, T>();
+  __shared__ double2 tab[kMixed ? 1 : T];
   if (!kMixed) {
-    cis_table_init(tab);
+    cis_table_init<T>(tab);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int bpc = (a.n_tiles + kWaves - 1) / kWaves;           // blocks per chunk
+  const int bpc = (a.n_tiles + kW - 1) / kW;                     // blocks per chunk
   const int64_t xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
   const int64_t chunk = (local / bpc) * kXcd + xcd;
-  const int tile = (int)(local % bpc) * kWaves + wid;
+  const int tile = (int)(local % bpc) * kW + wid;
   if (chunk >= a.n_chunks || tile >= a.n_tiles) return;          // uniform per wave
 
   LaneSrc L[NS];
@@ -217,7 +226,7 @@ __global__ __launch_bounds__(256, kMixed ? 7 : 8) void k_extract(ExtractArgs a, 
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const double ph = fma(u, p[i].l, fma(v, p[i].m, gg[t].z * p[i].n1));
-          const double2 cs = cis2pi_f64(ph, tab);
+          const double2 cs = cis2pi_f64<T>(ph, tab);
           const double x = fma(p[i].q11, qg[t].x, fma(p[i].q12x2, qg[t].y, fma(p[i].q22, qg[t].z, c0[i])));
           const double own = pow_m32_f64(x);                        // own model / spec, real after the shift
           enter_cell(L[i], acc, a.err, nproc, rint(__dmul_rn(u, p[i].theta)), rint(__dmul_rn(v, p[i].theta)));
@@ -497,13 +506,13 @@ __global__ __launch_bounds__(256) void k_extract_vp(ExtractArgs a, const double4
 
 // Resident blocks of an extraction kernel on the current device (cached).
 template <class K>
-int64_t resident_blocks(K kernel, int slot) {
-  static int64_t cache[2][16] = {};
+int64_t resident_blocks(K kernel, int slot, int threads) {
+  static int64_t cache[3][16] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
   if (!cache[slot][dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
       (void)hipGetLastError();
       return 0;
@@ -559,19 +568,19 @@ hipError_t launch_extract(const ExtractArgs &a0, int mixed, hipStream_t st, cons
     return hipGetLastError();
   }
   a.n_tiles = (a.n_src + 64 * ns - 1) / (64 * ns);
-  const int64_t bpc = (a.n_tiles + kWaves - 1) / kWaves;
-  auto kmixed = k_extract<true, kNsMixed, kGroupMixed>;
-  auto kf64 = k_extract<false, kNsF64, kGroupF64>;
-  const int64_t capacity = mixed ? resident_blocks(kmixed, 1) : resident_blocks(kf64, 0);
+  const bool big = !mixed && a.n_tiles >= kBigTableTiles;
+  const int waves = big ? waves_per_block<false, 2048>() : kWaves;
+  const int64_t bpc = (a.n_tiles + waves - 1) / waves;
+  auto kmixed = k_extract<true, kNsMixed, kGroupMixed, 1024>;   // (T unused: no table)
+  auto kf64 = k_extract<false, kNsF64, kGroupF64, 1024>;
+  auto kf64big = k_extract<false, kNsF64, kGroupF64, 2048>;
+  const int64_t capacity = mixed ? resident_blocks(kmixed, 1, 64 * kWaves)
+                                 : (big ? resident_blocks(kf64big, 2, 64 * waves) : resident_blocks(kf64, 0, 64 * kWaves));
   a.chunk = (int32_t)chunk_size(v.n_vis, bpc, capacity);
   a.n_chunks = (v.n_vis + a.chunk - 1) / a.chunk;
   const int64_t blocks = ((a.n_chunks + kXcd - 1) / kXcd) * kXcd * bpc;
-  if (mixed)
-    hipLaunchKernelGGL(kmixed, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.geo, v.quad, v.res, wt,
-                       a.acc.cell);
-  else
-    hipLaunchKernelGGL(kf64, dim3((unsigned)blocks), dim3(64 * kWaves), 0, st, a, v.geo, v.quad, v.res, wt,
-                       a.acc.cell);
+  auto kern = mixed ? kmixed : (big ? kf64big : kf64);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * waves), 0, st, a, v.geo, v.quad, v.res, wt, a.acc.cell);
   return hipGetLastError();
 }
 

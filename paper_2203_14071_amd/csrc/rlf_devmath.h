@@ -27,19 +27,23 @@
 
 namespace rlf {
 
-constexpr int kCisTable = 1024;                 // table steps per turn
+constexpr int kCisTable = 1024;                 // table steps per turn (the default table)
 
-// Fill the block's LDS table (kCisTable entries).  Call from every thread of
-// the block, followed by __syncthreads().
+// Fill the block's LDS table (T entries, T a power of two).  Call from every
+// thread of the block, followed by __syncthreads().
+template <int T = kCisTable>
 __device__ __forceinline__ void cis_table_init(double2 *tab) {
-  for (int k = threadIdx.x; k < kCisTable; k += blockDim.x) {
+  for (int k = threadIdx.x; k < T; k += blockDim.x) {
     double s, c;
-    sincospi((double)k * (2.0 / kCisTable), &s, &c);
+    sincospi((double)k * (2.0 / T), &s, &c);
     tab[k] = make_double2(c, s);
   }
 }
 
-constexpr double kTurnMagic = 6597069766656.0;   // 1.5 * 2^42: adding it rounds to 1/1024 turn
+// 1.5 * 2^52 / T: adding it rounds phi to a multiple of 1/T turn
+template <int T>
+constexpr double turn_magic() { return 1.5 * 4503599627370496.0 / T; }
+constexpr double kTurnMagic = turn_magic<kCisTable>();
 
 // Taylor coefficients of cos(2 pi d) and sin(2 pi d) in powers of d (turns):
 // -(2 pi)^2 / 2, (2 pi)^4 / 24; 2 pi, -(2 pi)^3 / 6, (2 pi)^5 / 120.
@@ -57,14 +61,24 @@ __device__ __forceinline__ double fma_vvs(double a, double b, double c) {
   return r;
 }
 
-// (cos 2 pi phi, sin 2 pi phi) with the table above.
+// (cos 2 pi phi, sin 2 pi phi) with a T-entry table.  T = 1024: |x| <= pi/1024
+// as described above.  T = 2048: |x| <= pi/2048 < 1.54e-3, and sin's x^5
+// term (< 7.2e-17) is dropped: sin to x^3 (truncation < x^5/5! < 7.2e-17,
+// below half an ulp of 1), cos to x^4 as before; fourteen VALU operations.
+template <int T = kCisTable>
 __device__ __forceinline__ double2 cis2pi_f64(double phi, const double2 *tab) {
-  const double m = phi + kTurnMagic;
-  const double d = phi - (m - kTurnMagic);       // turns, |d| <= 1/2048
+  static_assert(T == 1024 || T == 2048, "table sizes with a derived truncation bound");
+  constexpr double magic = turn_magic<T>();
+  const double m = phi + magic;
+  const double d = phi - (m - magic);            // turns, |d| <= 1/(2T)
   const double d2 = d * d;
   const double cx = fma(d2, fma_vvs(d2, kCos4, kCos2), 1.0);
-  const double sx = d * fma_vvs(d2, fma_vvs(d2, kSin5, kSin3), kSin1);
-  const double2 tv = tab[(uint32_t)__double2loint(m) & (uint32_t)(kCisTable - 1)];
+  double sx;
+  if constexpr (T == 1024)
+    sx = d * fma_vvs(d2, fma_vvs(d2, kSin5, kSin3), kSin1);
+  else
+    sx = d * fma_vvs(d2, kSin3, kSin1);
+  const double2 tv = tab[(uint32_t)__double2loint(m) & (uint32_t)(T - 1)];
   return make_double2(fma(tv.x, cx, -(tv.y * sx)), fma(tv.x, sx, tv.y * cx));
 }
 

@@ -12,7 +12,11 @@
 //               [0, 1) turns) in FP64, rounded to FP32 for v_sin/v_cos
 //               (argument in turns), profile and sum in FP32.
 // Two entry kernels: visibilities in caller order (rlf_model_vis), and the
-// residual in the facet object's uv-sorted order (extraction input).
+// residual in the facet object's uv-sorted order (extraction input).  Their
+// FP64 forms take a 2048-entry table (32 KB of LDS; sin's x^5 term drops,
+// one FMA per pair) in blocks of 512 threads, so that four blocks per CU
+// keep eight waves per SIMD in 128 KB of LDS; both form the sky sum with the
+// same table, so the two orders give the same residual values.
 #include "rlf_devmath.h"
 #include "rlf_internal.h"
 #include "rlf_sky.h"
@@ -21,11 +25,16 @@ namespace rlf {
 
 namespace {
 
+constexpr int kModelTable = 2048;                 // FP64 k_model's table entries
+
 template <bool kMixed>
-__global__ __launch_bounds__(256) void k_model(ModelArgs a) {
-  __shared__ double2 tab[kCisTable];
+constexpr int model_threads() { return kMixed ? 256 : 512; }
+
+template <bool kMixed>
+__global__ __launch_bounds__(model_threads<kMixed>()) void k_model(ModelArgs a) {
+  __shared__ double2 tab[kMixed ? 1 : kModelTable];
   if (!kMixed) {
-    cis_table_init(tab);
+    cis_table_init<kModelTable>(tab);
     __syncthreads();
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,7 +52,7 @@ __global__ __launch_bounds__(256) void k_model(ModelArgs a) {
   const double w = __dmul_rn(a.w_m[row], sc);
   const double spec = a.chan->spec[c];
   if (!kMixed) {
-    const double2 acc = sum_f64(u, v, w, a.src, a.s_begin, a.s_end, tab);
+    const double2 acc = sum_f64<kModelTable>(u, v, w, a.src, a.s_begin, a.s_end, tab);
     double2 *out = reinterpret_cast<double2 *>(a.out);
     double2 r;
     if (a.mode == 0) {
@@ -77,10 +86,10 @@ __global__ __launch_bounds__(256) void k_model(ModelArgs a) {
 // Residual (or a plain gather) into the uv-sorted order, plus the weights;
 // the FP64 form stores w R and w spec, the products its extraction uses.
 template <bool kMixed>
-__global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
-  __shared__ double2 tab[kCisTable];
+__global__ __launch_bounds__(model_threads<kMixed>(), kMixed ? 1 : 8) void k_residual_sorted(ResidualArgs a) {
+  __shared__ double2 tab[kMixed ? 1 : kModelTable];
   if (!kMixed && a.subtract) {
-    cis_table_init(tab);
+    cis_table_init<kModelTable>(tab);
     __syncthreads();
   }
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(256) void k_residual_sorted(ResidualArgs a) {
   if (!kMixed) {
     double2 r = reinterpret_cast<const double2 *>(a.vis)[i];
     if (a.subtract) {
-      const double2 acc = sum_f64(g.x, g.y, g.z, a.src, 0, a.n_src, tab);
+      const double2 acc = sum_f64<kModelTable>(g.x, g.y, g.z, a.src, 0, a.n_src, tab);
       r = make_double2(fma(-g.w, acc.x, r.x), fma(-g.w, acc.y, r.y));
     }
     // FP64 form: the weighted residual, and the weight times the spectral
@@ -165,20 +174,25 @@ hipError_t launch_update_sorted(const UpdateArgs &a, int mixed, hipStream_t st) 
 
 hipError_t launch_model(const ModelArgs &a, int mixed, hipStream_t st) {
   const int64_t n = a.n_rows * a.n_chan;
-  const int64_t blocks = (n + 255) / 256;
-  if (mixed)
-    hipLaunchKernelGGL(k_model<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_model<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  if (mixed) {
+    constexpr int t = model_threads<true>();
+    hipLaunchKernelGGL(k_model<true>, dim3((unsigned)((n + t - 1) / t)), dim3(t), 0, st, a);
+  } else {
+    constexpr int t = model_threads<false>();
+    hipLaunchKernelGGL(k_model<false>, dim3((unsigned)((n + t - 1) / t)), dim3(t), 0, st, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_residual_sorted(const ResidualArgs &a, int mixed, hipStream_t st) {
-  const int64_t blocks = (a.sv.n_vis + 255) / 256;
-  if (mixed)
-    hipLaunchKernelGGL(k_residual_sorted<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_residual_sorted<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  const int64_t n = a.sv.n_vis;
+  if (mixed) {
+    constexpr int t = model_threads<true>();
+    hipLaunchKernelGGL(k_residual_sorted<true>, dim3((unsigned)((n + t - 1) / t)), dim3(t), 0, st, a);
+  } else {
+    constexpr int t = model_threads<false>();
+    hipLaunchKernelGGL(k_residual_sorted<false>, dim3((unsigned)((n + t - 1) / t)), dim3(t), 0, st, a);
+  }
   return hipGetLastError();
 }
 

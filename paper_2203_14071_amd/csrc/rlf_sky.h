@@ -17,13 +17,15 @@
 
 namespace rlf {
 
+// T: entries of the exp table tab (1024 or 2048).
+template <int T = kCisTable>
 __device__ __forceinline__ double2 sum_f64(double u, double v, double w, const SrcModel *__restrict__ src, int b,
                                            int e, const double2 *tab) {
   const double uu = u * u, uv = u * v, vv = v * v;
   double ar = 0.0, ai = 0.0;
   auto term = [&](const SrcModel &p) {
     const double ph = fma(u, p.l, fma(v, p.m, w * p.n1));
-    const double2 cs = cis2pi_f64(ph, tab);
+    const double2 cs = cis2pi_f64<T>(ph, tab);
     const double x = fma(p.q11, uu, fma(p.q12x2, uv, fma(p.q22, vv, 1.0)));
     const double amp = p.flux * pow_m32_f64(x);             // (2/3) of the term's amplitude
     ar = fma(amp, cs.x, ar);

@@ -155,6 +155,12 @@ struct MixArgs {
 
 // One lane's work: a visibility (ops 0-1) or an ellipticity grid point
 // (ops 2-3) taken through `iters` passes of the kernel's own inner loop.
+// The FP64 sky-model mix as k_model runs it: a 2048-entry table in blocks
+// of 512 threads; the other mixes in blocks of 256.
+constexpr int kMixSkyTable = 2048;
+template <int OP>
+constexpr int mix_threads() { return OP == kMixSkyF64 ? 512 : 256; }
+
 template <int OP>
 __device__ __forceinline__ double mix_work(const MixArgs &a, int t, const double2 *tab) {
   double out = 0.0;
@@ -165,7 +171,7 @@ __device__ __forceinline__ double mix_work(const MixArgs &a, int t, const double
     for (int64_t it = 0; it < a.iters; ++it) {
       const double ui = u + (double)it;        // a new visibility each pass: nothing is loop-invariant
       if (OP == kMixSkyF64) {
-        const double2 z = rlf::sum_f64(ui, v, w, a.src, 0, a.n_items, tab);
+        const double2 z = rlf::sum_f64<kMixSkyTable>(ui, v, w, a.src, 0, a.n_items, tab);
         ar += z.x;
         ai += z.y;
       } else {
@@ -240,10 +246,10 @@ __device__ __forceinline__ uint64_t fixed_clock() {
 // the loop's loads as possibly clobbered and issue vector loads in place of
 // the kernels' scalar loads.)
 template <int OP>
-__global__ __launch_bounds__(256) void k_mix(MixArgs a) {
-  __shared__ double2 tab[rlf::kCisTable];
+__global__ __launch_bounds__(mix_threads<OP>()) void k_mix(MixArgs a) {
+  __shared__ double2 tab[OP == kMixSkyF64 ? kMixSkyTable : 1];
   if (OP == kMixSkyF64) {
-    rlf::cis_table_init(tab);
+    rlf::cis_table_init<kMixSkyTable>(tab);
     __syncthreads();
   }
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,9 +269,14 @@ __global__ __launch_bounds__(256) void k_mix(MixArgs a) {
   a.sink[t] = mix_work<OP>(a, t, tab);
 }
 
+// `blocks` counts blocks of 256 threads; the FP64 sky-model mix runs the same
+// threads in blocks of 512 (blocks must then be even)
 hipError_t launch_mix(int op, int blocks, const MixArgs &a, hipStream_t st) {
   switch (op) {
-    case kMixSkyF64: hipLaunchKernelGGL(k_mix<kMixSkyF64>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kMixSkyF64:
+      if (blocks % 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_mix<kMixSkyF64>, dim3(blocks / 2), dim3(mix_threads<kMixSkyF64>()), 0, st, a);
+      break;
     case kMixSkyMixed: hipLaunchKernelGGL(k_mix<kMixSkyMixed>, dim3(blocks), dim3(256), 0, st, a); break;
     case kMixFitF64: hipLaunchKernelGGL(k_mix<kMixFitF64>, dim3(blocks), dim3(256), 0, st, a); break;
     case kMixFitMixed: hipLaunchKernelGGL(k_mix<kMixFitMixed>, dim3(blocks), dim3(256), 0, st, a); break;

@@ -240,8 +240,9 @@ __global__ __launch_bounds__((64 * waves_per_block<kMixed, T>()), kMixed ? 7 : 8
     }
   } else {
     // (the flux stays a multiplication here: folded into the profile
-    // argument as in the FP64 form it saved an instruction per pair but
-    // measured 0.6 % slower on the 10,000-source field)
+    // argument as in the FP64 form it saves an instruction per pair but
+    // measured 0.6 % slower on the 10,000-source field, and again 0.8 %
+    // slower on the 1000-source field with the kernel as it is now)
     SrcMixed p[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) p[i] = a.src32[src[i]];

@@ -52,12 +52,12 @@ MODEL_FLOP_PAIR = 19
 # bracket) at this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE (each
 # scaled by a plain copy's reading), for the kernels as they are now; None
 # where not measured.  profiles/step_kernels_ska_mid_1k_{fp64,mixed}.md:
-#   extraction (k_extract): fetch 1737.6 / 1189.9 MB, write 1096.4 / 983.3 MB
-#   likelihood (k_fit + k_estimate): fetch 155.4 + 150.2 / 79.4 + 146.5 MB,
+#   extraction (k_extract): fetch 1996.7 / 1189.4 MB, write 1096.5 / 983.3 MB
+#   likelihood (k_fit + k_estimate): fetch 155.4 + 150.2 / 79.4 + 146.6 MB,
 #     write 51.3 + 0.3 / 51.3 + 0.8 MB
-#   sky model (k_model): fetch 372.7 / 298.5 MB, write 148.3 / 74.1 MB
-TRAFFIC_BYTES = {"fp64": {"extract": 2834.0e6, "fit": 357.2e6, "model": 521.0e6},
-                 "mixed": {"extract": 2173.2e6, "fit": 278.0e6, "model": 372.6e6}}
+#   sky model (k_model): fetch 372.7 / 298.7 MB, write 148.3 / 74.1 MB
+TRAFFIC_BYTES = {"fp64": {"extract": 3093.2e6, "fit": 357.2e6, "model": 521.0e6},
+                 "mixed": {"extract": 2172.7e6, "fit": 278.1e6, "model": 372.8e6}}
 # VALU roofline in lane-slots: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
 # Work per unit = the method's necessary operations in each form (not a
 # compiled count), priced with gfx950's measured rates (the VALU probe,
@@ -103,10 +103,10 @@ SLOTS = {f: {k: round(sum(v.values()), 3) for k, v in d.items()} for f, d in SLO
 # rate: slots = VALU instructions with each v_rsq_f64 counted 4, per CU per
 # cycle at that clock.  The VALU probe (probe/valu_probe.hip, run by the
 # benchmark) measures what instruction streams of each kind reach.
-VALU_WORK = {"fp64": {"extract": (5.969e9, 1.48e8, 2.171e9), "fit": (5.750e9, 5.90e8, 2.246e9),
-                      "model": (4.236e9, 1.45e8, 2.017e9)},
-             "mixed": {"extract": (4.745e9, 0.0, 2.314e9), "fit": (4.853e9, 4.16e6, 2.336e9),
-                       "model": (2.321e9, 0.0, 2.218e9)}}
+VALU_WORK = {"fp64": {"extract": (5.821e9, 1.48e8, 2.268e9), "fit": (5.193e9, 5.90e8, 2.322e9),
+                      "model": (4.091e9, 1.45e8, 2.057e9)},
+             "mixed": {"extract": (4.745e9, 0.0, 2.330e9), "fit": (4.267e9, 4.16e6, 2.350e9),
+                       "model": (2.321e9, 0.0, 2.245e9)}}
 
 
 def log(*a):

@@ -22,7 +22,7 @@
 //
 // Position marginalisation (Sec. 2.4; n_pos offsets x_p on a square grid,
 // uniform prior): D is formed per offset from the cross-correlation data
-// G[c, p] = W_c Re(Vbar_c exp(-2 pi i k_c.x_p)) and M is shared,
+// G[c, p] = sqrt(W_c) Re(Vbar_c exp(-2 pi i k_c.x_p)) and M is shared,
 //   ln L(e) = ln sum_k w_k (1/n_pos) sum_p exp(D_kp^2 / (2 M_k) - ln(M_k) / 2).
 // The knots run in blocks of KB with the KB * n_pos sums of a block in
 // registers; the n_pos values of a cell come in through scalar loads (one

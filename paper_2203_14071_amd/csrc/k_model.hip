@@ -5,7 +5,7 @@
 // records come in two at a time through scalar loads shared by the wave.  Work per
 // (visibility, source) pair:
 //   FP64 form:  phase (3 FMA), exp(2 pi i phase) by exact reduction + LDS
-//               table + short polynomials (~15 ops), profile
+//               table + short polynomials (14 ops), profile
 //               (3 FMA + corrected rsqrt cube, 5 ops, + 1 MUL), 2 FMA into the
 //               sum (the profile's constant 3/2 is applied once at the end);
 //   mixed form: phase and its fractional part (v_fract_f64, exact, in

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -310,6 +311,17 @@ __global__ __launch_bounds__(256) void k_rsq64_error(int64_t n, double *block_ma
   if (threadIdx.x == 0) block_max[blockIdx.x] = sh[0];
 }
 
+// exp(2 pi i phi) by the library's table method (cis2pi_f64) at given
+// phases, for each table size the kernels use; a grid-stride loop.
+template <int T>
+__global__ __launch_bounds__(256) void k_cis_eval(const double *phi, int64_t n, double2 *out) {
+  __shared__ double2 tab[T];
+  rlf::cis_table_init<T>(tab);
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = rlf::cis2pi_f64<T>(phi[i], tab);
+}
+
 extern "C" {
 
 // Number of probe kernels.
@@ -487,6 +499,31 @@ int valu_probe_rsq64_error(int64_t n, double *max_rel) {
   double worst = 0.0;
   for (int b = 0; b < kBlocks && e == hipSuccess; ++b) worst = h[b] > worst ? h[b] : worst;
   *max_rel = worst;
+  return (int)e;
+}
+
+// (cos 2 pi phi, sin 2 pi phi) by the kernels' table method with a table of
+// `table` entries (1024 or 2048), for n phases in turns (host arrays:
+// phi_host [n], out_host [2 n] as cos, sin pairs; |phi| < 2^40).
+int valu_probe_cis(int table, const double *phi_host, int64_t n, double *out_host) {
+  if ((table != 1024 && table != 2048) || n < 1 || n > (int64_t)1 << 24 || !phi_host || !out_host)
+    return (int)hipErrorInvalidValue;
+  double *dp = nullptr;
+  double2 *dout = nullptr;
+  hipError_t e = hipMalloc(&dp, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double2) * n);
+  if (e == hipSuccess) e = hipMemcpy(dp, phi_host, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    if (table == 1024)
+      hipLaunchKernelGGL(k_cis_eval<1024>, dim3(blocks), dim3(256), 0, 0, dp, n, dout);
+    else
+      hipLaunchKernelGGL(k_cis_eval<2048>, dim3(blocks), dim3(256), 0, 0, dp, n, dout);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out_host, dout, sizeof(double2) * n, hipMemcpyDeviceToHost);
+  if (dp) (void)hipFree(dp);
+  if (dout) (void)hipFree(dout);
   return (int)e;
 }
 

@@ -322,6 +322,13 @@ __global__ __launch_bounds__(256) void k_cis_eval(const double *phi, int64_t n, 
     out[i] = rlf::cis2pi_f64<T>(phi[i], tab);
 }
 
+// (2/3) x^(-3/2) by the kernels' corrected rsqrt cube (pow_m32_f64) at given
+// arguments x >= 1; a grid-stride loop.
+__global__ __launch_bounds__(256) void k_pow_m32_eval(const double *x, int64_t n, double *out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = rlf::pow_m32_f64(x[i]);
+}
+
 extern "C" {
 
 // Number of probe kernels.
@@ -523,6 +530,25 @@ int valu_probe_cis(int table, const double *phi_host, int64_t n, double *out_hos
   }
   if (e == hipSuccess) e = hipMemcpy(out_host, dout, sizeof(double2) * n, hipMemcpyDeviceToHost);
   if (dp) (void)hipFree(dp);
+  if (dout) (void)hipFree(dout);
+  return (int)e;
+}
+
+// (2/3) x^(-3/2) by the kernels' corrected rsqrt cube for n arguments
+// x >= 1 (host arrays x_host [n], out_host [n]).
+int valu_probe_pow_m32(const double *x_host, int64_t n, double *out_host) {
+  if (n < 1 || n > (int64_t)1 << 24 || !x_host || !out_host) return (int)hipErrorInvalidValue;
+  double *dx = nullptr, *dout = nullptr;
+  hipError_t e = hipMalloc(&dx, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMemcpy(dx, x_host, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_pow_m32_eval, dim3(blocks), dim3(256), 0, 0, dx, n, dout);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out_host, dout, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (dx) (void)hipFree(dx);
   if (dout) (void)hipFree(dout);
   return (int)e;
 }

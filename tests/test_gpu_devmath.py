@@ -1,4 +1,7 @@
-"""The kernels' FP64 exp(2 pi i phi) (the exact reduction to 1/T turn, a
+"""The kernels' FP64 elementary functions against extended-precision
+references.
+
+exp(2 pi i phi) (the exact reduction to 1/T turn, a
 T-entry table and short Taylor polynomials; T = 1024 and T = 2048) against
 an extended-precision reference, over phases the sky model and the
 extraction meet (a few thousand turns) and far beyond (up to 2^39 turns),
@@ -50,3 +53,24 @@ def test_table_exp_matches_extended_precision(table):
     worst = max(err_c.max(), err_s.max())
     print(f"T = {table}: max |error| {worst:.3e} (cos {err_c.max():.3e}, sin {err_s.max():.3e}) over {phi.size} phases")
     assert worst <= 4.1e-16
+
+
+def test_profile_power_matches_extended_precision():
+    """pow_m32_f64(x) = (2/3) x^(-3/2) from v_rsq_f64 and one correction,
+    y^3 (5/3 - x y^2): with e = 1 - x y^2 the correction leaves a relative
+    error of (15/8) e^2, below 2.7e-14 for |e| <= 2^-23, plus a few
+    roundings; arguments 1 + s q from 1 to 2^40 (measured: 2.0e-14, so the
+    instruction's error reaches about 2^-23.2 at some of these arguments,
+    more than the 2^-24.2 of the probe's log-uniform sweep)."""
+    assert os.path.exists(build.PROBE_LIB), "probe library not built"
+    lib = ctypes.CDLL(build.PROBE_LIB)
+    lib.valu_probe_pow_m32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    rng = np.random.default_rng(3)
+    x = np.ascontiguousarray(np.concatenate([np.exp2(rng.uniform(0.0, 40.0, 1 << 20)), [1.0, 2.0, 4.0, 2.0 ** 40]]))
+    out = np.empty_like(x)
+    assert lib.valu_probe_pow_m32(x.ctypes.data, x.size, out.ctypes.data) == 0
+    xl = x.astype(np.longdouble)
+    ref = (np.longdouble(2) / 3) / (xl * np.sqrt(xl))
+    rel = np.abs((out.astype(np.longdouble) - ref) / ref).astype(np.float64)
+    print(f"pow_m32_f64: max relative error {rel.max():.3e} over {x.size} arguments")
+    assert rel.max() < 3e-14

@@ -420,3 +420,43 @@ def test_zero_flux_sources(precision):
         c.facets_create(obs, bad, prior_mu=mu)
     assert e.value.code == rlf.RLF_EINVAL
     c.close()
+
+
+def test_extraction_table_sizes_agree():
+    """The FP64 extraction takes a 2048-entry exp table for launches of at
+    least 8 source tiles (512 sources) and a 1024-entry one below: 600
+    sources extracted together (10 tiles) and the same sources in two
+    halves (5 tiles each) give the same cells, counts and weight sums
+    (weight sums to their summation order, exact or within a few ulp) and
+    facet averages within the two tables' difference (each within 2.3e-16
+    of exp(2 pi i phi) per term)."""
+    cfg = synth.CONFIGS[0]
+    o = synth.observation(0, cfg)
+    cat = G.circular(synth.catalogue(cfg, synth.rng(0, synth.STREAM_CAT + 11), 600))
+    rng = np.random.default_rng(11)
+    n = o.n_rows * o.n_chan
+    resid = cfg.noise_sigma_jy * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    c = rlf.Context(0)
+    obs = G.make_obs(o, resid)
+
+    def extract(sub):
+        f = c.facets_create(obs, sub)
+        c.extract_facets(obs, sub, obs.vis, f)
+        fac = f.copy()
+        f.free()
+        return fac
+
+    full = extract(cat)
+    halves = [extract(cat.subset(np.arange(0, 300))), extract(cat.subset(np.arange(300, 600)))]
+    scale = float(np.max(np.abs(resid)))
+    for s in range(cat.n_src):
+        h, t = halves[s // 300], s % 300
+        a, b = int(full["offsets"][s]), int(full["offsets"][s + 1])
+        ha, hb = int(h["offsets"][t]), int(h["offsets"][t + 1])
+        assert b - a == hb - ha > 0, s
+        for key in ("ix", "iy", "count"):
+            assert np.array_equal(full[key][a:b], h[key][ha:hb]), (s, key)
+        assert np.allclose(full["wsum"][a:b], h["wsum"][ha:hb], rtol=1e-13, atol=0), s
+        tol = 1e-14 * (scale + cat.flux_jy[s])
+        assert np.max(np.abs(full["vbar"][a:b] - h["vbar"][ha:hb])) <= tol, s
+    c.close()
